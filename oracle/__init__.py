@@ -1,0 +1,206 @@
+"""CPU oracle for MRG32k3a / MRG31k3p multi-stream generation.
+
+TEST INFRASTRUCTURE ONLY: tests/, the smoke check in __graft_entry__.py and
+the cpu_baseline leg of bench.py may import this package; the product library
+(paper_2201_06604_amd) never does.  The arithmetic lives in mrg_oracle.c (and
+fisher_oracle.c); this module only marshals numpy arrays through ctypes.
+
+Generator ids: 1 = MRG32k3a, 2 = MRG31k3p.  Stream records are 18 uint32
+words: current state, initial state, substream start (6 words each), in the
+generator's own word order (MRG32k3a oldest-first, MRG31k3p newest-first as
+printed in the paper's stream table of Section 2.1).
+"""
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+MRG32K3A = 1
+MRG31K3P = 2
+UNIFORM, NORMAL, EXPONENTIAL, RAW = 0, 1, 2, 3
+F64, F32, U32 = 0, 1, 2
+REC = 18
+
+_NP_DTYPE = {F64: np.float64, F32: np.float32, U32: np.uint32}
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """Load liboracle.so, building it with gcc first if it is missing."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH):
+                from . import build as _b
+                _b.build()
+            L = ctypes.CDLL(_LIB_PATH)
+            u32p = ctypes.POINTER(ctypes.c_uint32)
+            u64p = ctypes.POINTER(ctypes.c_uint64)
+            vp = ctypes.c_void_p
+            c_int, c_u64, c_dbl = ctypes.c_int, ctypes.c_uint64, ctypes.c_double
+            sig = {
+                "orc_output": (c_u64, [c_int, c_u64, c_u64]),
+                "orc_step": (c_u64, [c_int, u32p]),
+                "orc_norm": (c_dbl, [c_int]),
+                "orc_uniform_f64": (c_dbl, [c_int, c_u64]),
+                "orc_f32_rz": (ctypes.c_float, [c_dbl]),
+                "orc_box_muller": (None, [c_dbl, c_dbl, ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl)]),
+                "orc_exponential": (c_dbl, [c_dbl, c_dbl]),
+                "orc_matpow": (None, [c_int, c_int, u64p, c_int, u64p]),
+                "orc_jump": (None, [c_int, u32p, u64p, c_int]),
+                "orc_seed_valid": (c_int, [c_int, u64p]),
+                "orc_create_streams": (None, [c_int, u32p, c_u64, u32p]),
+                "orc_next_substream": (None, [c_int, u32p, c_u64]),
+                "orc_reset_substream": (None, [u32p, c_u64]),
+                "orc_reset_stream": (None, [u32p, c_u64]),
+                "orc_advance": (None, [c_int, u32p, c_u64, c_u64]),
+                "orc_stream_draws": (c_int, [c_int, u32p, c_u64, c_int, c_int, c_dbl, vp, c_u64]),
+                "orc_generate_range": (c_int, [c_int, u32p, c_u64, c_u64, c_int, c_int, c_dbl, vp,
+                                               c_u64, c_u64]),
+                "orc_generate": (c_int, [c_int, u32p, c_u64, c_u64, c_int, c_int, c_dbl, vp]),
+            }
+            for name, (res, args) in sig.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+    return _lib
+
+
+def _u32p(a):
+    assert a.dtype == np.uint32 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def _u64p(a):
+    assert a.dtype == np.uint64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+def _words(e: int):
+    """Non-negative Python int -> little-endian uint64 words."""
+    assert e >= 0
+    words = []
+    while True:
+        words.append(e & (2**64 - 1))
+        e >>= 64
+        if e == 0:
+            break
+    return np.array(words, dtype=np.uint64)
+
+
+# ---------------------------------------------------------------- primitives
+def output(gen, x1, x2):
+    return int(lib().orc_output(gen, x1, x2))
+
+
+def step(gen, state):
+    """Advance a 6-word state (numpy uint32, in place) one step; return z."""
+    return int(lib().orc_step(gen, _u32p(state)))
+
+
+def norm(gen):
+    return float(lib().orc_norm(gen))
+
+
+def uniform_f64(gen, z):
+    return float(lib().orc_uniform_f64(gen, z))
+
+
+def f32_rz(u):
+    return np.float32(lib().orc_f32_rz(u))
+
+
+def box_muller(u1, u2):
+    x, y = ctypes.c_double(), ctypes.c_double()
+    lib().orc_box_muller(u1, u2, ctypes.byref(x), ctypes.byref(y))
+    return x.value, y.value
+
+
+def exponential(u, rate=1.0):
+    return float(lib().orc_exponential(u, rate))
+
+
+def matpow(gen, comp, e: int):
+    """A_comp^e as a 3x3 list of Python ints (oldest-first coordinates)."""
+    w = _words(e)
+    out = np.zeros(9, dtype=np.uint64)
+    lib().orc_matpow(gen, comp, _u64p(w), len(w), _u64p(out))
+    return [[int(out[3 * r + c]) for c in range(3)] for r in range(3)]
+
+
+def jump(gen, state, e: int):
+    """Advance a 6-word state (in place) by e steps via matrix powers."""
+    w = _words(e)
+    lib().orc_jump(gen, _u32p(state), _u64p(w), len(w))
+
+
+def seed_valid(gen, seed):
+    s = np.array([int(v) for v in seed], dtype=np.uint64)
+    return bool(lib().orc_seed_valid(gen, _u64p(s)))
+
+
+# ------------------------------------------------------------------- streams
+def create_streams(gen, creator, n):
+    """n stream records (n x 18 uint32); `creator` (6 uint32) advances in place."""
+    out = np.zeros((n, REC), dtype=np.uint32)
+    lib().orc_create_streams(gen, _u32p(creator), n, _u32p(out))
+    return out
+
+
+def next_substream(gen, streams):
+    lib().orc_next_substream(gen, _u32p(streams), streams.shape[0])
+
+
+def reset_substream(streams):
+    lib().orc_reset_substream(_u32p(streams), streams.shape[0])
+
+
+def reset_stream(streams):
+    lib().orc_reset_stream(_u32p(streams), streams.shape[0])
+
+
+def advance(gen, streams, k):
+    lib().orc_advance(gen, _u32p(streams), streams.shape[0], k)
+
+
+def stream_draws(gen, cur, cnt, dist=UNIFORM, dtype=F64, param=1.0):
+    """cnt draws of one stream; `cur` (6 uint32) advances in place."""
+    out = np.zeros(cnt, dtype=_NP_DTYPE[dtype])
+    rc = lib().orc_stream_draws(gen, _u32p(cur), cnt, dist, dtype, param,
+                                out.ctypes.data_as(ctypes.c_void_p), 1)
+    assert rc == 0
+    return out
+
+
+def generate(gen, streams, n, dist=UNIFORM, dtype=F64, param=1.0, threads=1):
+    """n numbers from the streams (n_streams x 18, advanced in place) with
+    out[k*S + s] = draw k of stream s.  `threads` > 1 splits the streams over
+    Python threads (the C code releases the GIL)."""
+    S = streams.shape[0]
+    out = np.zeros(n, dtype=_NP_DTYPE[dtype])
+    ptr = out.ctypes.data_as(ctypes.c_void_p)
+    if threads <= 1 or S < 2:
+        rc = lib().orc_generate(gen, _u32p(streams), S, n, dist, dtype, param, ptr)
+        assert rc == 0
+        return out
+    bounds = np.linspace(0, S, threads + 1).astype(np.int64)
+    rcs = []
+
+    def work(b0, b1):
+        rcs.append(lib().orc_generate_range(gen, _u32p(streams), S, n, dist, dtype, param, ptr,
+                                            int(b0), int(b1)))
+
+    ts = [threading.Thread(target=work, args=(bounds[i], bounds[i + 1])) for i in range(threads)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert all(rc == 0 for rc in rcs)
+    return out
