@@ -1,0 +1,185 @@
+/*
+ * mrg355.h -- C ABI of the MI355X (gfx950) multi-stream MRG32k3a generator.
+ *
+ * The calls follow the problem as the clrng paper states it (Xu, Brown,
+ * L'Ecuyer, "clrng: A tool set for parallel random number generation on GPUs
+ * in R"): create streams from a 6-integer seed (Section 2.1), generate n
+ * numbers of a distribution and dtype from explicit streams (Sections 2.2,
+ * 3.1, 3.2), save and restore stream state (Section 2.2, save/restore
+ * example).  The generator is MRG32k3a (L'Ecuyer 1999), the one the paper
+ * names as prior art and future work (Sections 1, 2, 6).
+ *
+ * Conventions (every entry point):
+ *   - Returns mrg_status: MRG_OK (0) or a negative error.  mrg_last_error()
+ *     returns a thread-local message for the last failing call.
+ *   - Arguments are validated before any side effect: on error no kernel is
+ *     launched, no device memory is written and no creator is advanced.
+ *   - Device work is enqueued asynchronously on the caller's hipStream_t
+ *     (NULL = the default stream).  Faults of already enqueued kernels
+ *     surface at the next synchronising HIP call.
+ *   - The caller owns every device buffer (stream records, outputs).  The
+ *     library allocates no device memory in these calls.
+ *   - "device pointer" means memory from hipMalloc (or a torch CUDA tensor);
+ *     "host pointer" means ordinary host memory.
+ *   - Not thread-safe per stream array: two calls that touch the same stream
+ *     records must be ordered by the caller (same hipStream or events).
+ */
+#ifndef MRG355_H
+#define MRG355_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MRG_ABI_VERSION 1
+
+typedef enum {
+    MRG_OK = 0,
+    MRG_E_INVALID_ARG = -1,   /* null pointer, bad enum, size or alignment   */
+    MRG_E_INVALID_SEED = -2,  /* seed violates the validity rule             */
+    MRG_E_UNSUPPORTED = -3,   /* generator/dist/dtype combination not built  */
+    MRG_E_HIP = -4,           /* a HIP runtime call failed                   */
+    MRG_E_NOMEM = -5,         /* host allocation failed / buffer too small   */
+    MRG_E_CORRUPT_STATE = -6  /* import: bad magic, version, length or words */
+} mrg_status;
+
+/* Generators.  MRG32k3a: components mod m1 = 2^32-209 and m2 = 2^32-22853,
+ * streams 2^127 apart, substreams 2^76 apart.  (Id 2 is reserved for the
+ * paper's own MRG31k3p.) */
+typedef enum { MRG_GEN_MRG32K3A = 1, MRG_GEN_MRG31K3P = 2 } mrg_generator;
+
+/* Distributions (Sections 2.2, 3.1, 3.2):
+ *   MRG_UNIFORM      u = z / (m1 + 1), strictly inside (0,1)
+ *   MRG_NORMAL       Box-Muller (Algorithm 1) on consecutive uniforms of one
+ *                    stream: draws 2p, 2p+1 = R cos(2 pi u2), R sin(2 pi u2)
+ *                    with R = sqrt(-2 log u1), (u1,u2) = steps 2p, 2p+1
+ *   MRG_EXPONENTIAL  -log(u) / rate, rate = `param` (> 0, finite)
+ *   MRG_RAW          the integer z in [1, m1] itself (dtype MRG_U32 only)  */
+typedef enum { MRG_UNIFORM = 0, MRG_NORMAL = 1, MRG_EXPONENTIAL = 2, MRG_RAW = 3 } mrg_dist;
+
+/* Output element types.  F32 uniforms are the double uniform rounded toward
+ * zero (so they stay below 1); F32 normals/exponentials are the double value
+ * rounded to nearest.  U32 pairs only with MRG_RAW, and MRG_RAW only with U32. */
+typedef enum { MRG_F64 = 0, MRG_F32 = 1, MRG_U32 = 2 } mrg_dtype;
+
+/* The creator: the state the next created stream starts from (the paper's
+ * hidden .Random.seed.clrng object, Section 2.1), as an explicit value. */
+typedef struct {
+    uint32_t s[6];
+} mrg_creator;
+
+/* One stream (Section 2.1: current state and initial state; plus the start of
+ * the current substream).  Each 6-word state is (x1[n-3], x1[n-2], x1[n-1],
+ * x2[n-3], x2[n-2], x2[n-1]): oldest first per component.  72 bytes. */
+typedef struct {
+    uint32_t cur[6];
+    uint32_t start[6];
+    uint32_t sub[6];
+} mrg_stream;
+
+typedef enum {
+    MRG_RESET_STREAM = 0,     /* cur = sub = start                 */
+    MRG_RESET_SUBSTREAM = 1,  /* cur = sub                         */
+    MRG_NEXT_SUBSTREAM = 2    /* sub = A^(2^76) sub; cur = sub      */
+} mrg_reset_kind;
+
+/* Launch shape of mrg_generate_ex.  Results never depend on it: the output
+ * position and every value are functions of (stream, draw index) only.
+ *   block      threads per block: 64, 128, 256, 512 or 1024
+ *   chunk      draws (normal: pairs) per work-item, >= 1; 0 = automatic
+ *   nontemporal 1 = stream the output with non-temporal stores
+ *   arith      0 = automatic, 1 = 32x32->64 integer mod arithmetic,
+ *              2 = the same integers carried exactly in fp64 FMA registers */
+typedef struct {
+    uint32_t block;
+    uint32_t chunk;
+    uint32_t nontemporal;
+    uint32_t arith;
+} mrg_launch_cfg;
+
+int         mrg_abi_version(void);
+const char* mrg_status_string(mrg_status status);
+const char* mrg_last_error(void);
+
+/* Seed rule (RngStreams'; the paper states none): words 0-2 below m1, words
+ * 3-5 below m2, neither triple all zero.  MRG_E_INVALID_SEED otherwise; a
+ * seed is never reduced mod m.  `seed` is a host pointer to 6 words. */
+mrg_status mrg_seed_check(mrg_generator gen, const uint32_t seed[6]);
+
+/* setBaseCreator (Section 2.1): creator := seed after mrg_seed_check. */
+mrg_status mrg_creator_init(mrg_generator gen, mrg_creator* creator, const uint32_t seed[6]);
+
+/* createStreamsCpu (Section 2.1): n streams into host memory `host_out`
+ * (n records).  Stream i starts at the creator advanced i * 2^127 steps
+ * (cur = start = sub); the creator then advances n * 2^127 steps.  n = 0 is
+ * a no-op. */
+mrg_status mrg_streams_create_host(mrg_generator gen, mrg_creator* creator, size_t n,
+                                   mrg_stream* host_out);
+
+/* createStreamsGpu (Section 2.1): the same n streams written by a kernel to
+ * device memory `dev_out` (n records, 4-byte aligned).  Identical records
+ * to mrg_streams_create_host; the creator (host value) advances the same
+ * way once the launch has been enqueued. */
+mrg_status mrg_streams_create_device(mrg_generator gen, mrg_creator* creator, size_t n,
+                                     mrg_stream* dev_out, hipStream_t stream);
+
+/* Substream resets on n device stream records (see mrg_reset_kind). */
+mrg_status mrg_streams_reset(mrg_generator gen, mrg_stream* dev, size_t n, mrg_reset_kind kind,
+                             hipStream_t stream);
+
+/* Advance the current state of n device stream records by `steps` steps. */
+mrg_status mrg_streams_advance(mrg_generator gen, mrg_stream* dev, size_t n, uint64_t steps,
+                               hipStream_t stream);
+
+/* runifGpu / rnormGpu / rexpGpu (Sections 2.2, 3.1, 3.2): n numbers from
+ * the n_streams device stream records `dev` into device memory `dev_out`.
+ * Stream s makes cnt_s = floor(n/S) + (s < n mod S) draws and draw k of
+ * stream s is stored at element k*S + s (S = n_streams): the output is a
+ * dense array of n elements whose layout does not depend on the launch.
+ * Each stream's current state advances by the steps it consumed (cnt_s;
+ * normals 2*ceil(cnt_s/2)).  `param` is the rate of MRG_EXPONENTIAL and is
+ * ignored otherwise.  dev_out must be aligned to its element size.
+ * n = 0 is a no-op.  Errors: MRG_E_INVALID_ARG (null pointers, n_streams = 0
+ * with n > 0, dist/dtype mismatch, bad rate, misalignment, n_streams above
+ * 2^31). */
+mrg_status mrg_generate(mrg_generator gen, mrg_stream* dev, size_t n_streams, uint64_t n,
+                        mrg_dist dist, mrg_dtype dtype, double param, void* dev_out,
+                        hipStream_t stream);
+
+/* mrg_generate with an explicit launch shape (NULL = automatic).  Bitwise the
+ * same results for every valid cfg. */
+mrg_status mrg_generate_ex(mrg_generator gen, mrg_stream* dev, size_t n_streams, uint64_t n,
+                           mrg_dist dist, mrg_dtype dtype, double param, void* dev_out,
+                           const mrg_launch_cfg* cfg, hipStream_t stream);
+
+/* Save/restore (Section 2.2, saveRDS/readRDS example).  Byte format,
+ * little-endian: "MRG3", u32 version = 1, u32 generator, u32 flags (bit 0:
+ * a creator follows the streams), u64 n, n x 18 u32 (cur, start, sub),
+ * [6 u32 creator].
+ *
+ * mrg_streams_export_size: bytes needed for n streams (+ creator).
+ * mrg_streams_export: copies n device records to host memory `host_buf`
+ * (capacity `cap` bytes), appends `creator` when non-NULL, sets *len, and
+ * returns after `stream` has been synchronised.
+ * mrg_streams_import: validates the whole buffer (magic, version, generator,
+ * length, every state word below its modulus, no all-zero triple) and only
+ * then copies its n records to `dev` (room for `n` records required) and,
+ * when `creator` is non-NULL and the buffer holds one, restores it.  Returns
+ * after the copy has completed.  *n_out (optional) receives the count. */
+mrg_status mrg_streams_export_size(size_t n, int with_creator, size_t* bytes);
+mrg_status mrg_streams_export(mrg_generator gen, const mrg_stream* dev, size_t n,
+                              const mrg_creator* creator, void* host_buf, size_t cap, size_t* len,
+                              hipStream_t stream);
+mrg_status mrg_streams_import(mrg_generator gen, const void* host_buf, size_t len, mrg_stream* dev,
+                              size_t n, size_t* n_out, mrg_creator* creator, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRG355_H */

@@ -54,6 +54,7 @@ def lib():
                 "orc_exponential": (c_dbl, [c_dbl, c_dbl]),
                 "orc_matpow": (None, [c_int, c_int, u64p, c_int, u64p]),
                 "orc_jump": (None, [c_int, u32p, u64p, c_int]),
+                "orc_jump_many": (None, [c_int, u32p, c_u64, c_u64, u64p, c_int]),
                 "orc_seed_valid": (c_int, [c_int, u64p]),
                 "orc_create_streams": (None, [c_int, u32p, c_u64, u32p]),
                 "orc_next_substream": (None, [c_int, u32p, c_u64]),
@@ -139,6 +140,13 @@ def jump(gen, state, e: int):
     """Advance a 6-word state (in place) by e steps via matrix powers."""
     w = _words(e)
     lib().orc_jump(gen, _u32p(state), _u64p(w), len(w))
+
+
+def jump_many(gen, states, e: int):
+    """Advance every row of a (n, 6) uint32 array (in place) by e steps."""
+    assert states.ndim == 2 and states.shape[1] == 6
+    w = _words(e)
+    lib().orc_jump_many(gen, _u32p(states), states.shape[0], 6, _u64p(w), len(w))
 
 
 def seed_valid(gen, seed):

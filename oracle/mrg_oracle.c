@@ -241,17 +241,29 @@ static void mat_vec(uint64_t m, const uint64_t M[9], int64_t v[3]) {
     memcpy(v, t, sizeof(t));
 }
 
+/* Apply the two component matrices M[0], M[1] to an external state. */
+static void apply(const orc_gen* g, uint64_t M[2][9], uint32_t state[6]) {
+    int64_t x[2][3];
+    to_internal(g, state, x);
+    for (int j = 0; j < 2; ++j) mat_vec((uint64_t)g->m[j], M[j], x[j]);
+    to_external(g, x, state);
+}
+
 /* Advance an external state by e steps (e as little-endian words). */
 void orc_jump(int gen, uint32_t state[6], const uint64_t* e, int nwords) {
     const orc_gen* g = gen_of(gen);
-    int64_t x[2][3];
-    to_internal(g, state, x);
-    for (int j = 0; j < 2; ++j) {
-        uint64_t M[9];
-        orc_matpow(gen, j, e, nwords, M);
-        mat_vec((uint64_t)g->m[j], M, x[j]);
-    }
-    to_external(g, x, state);
+    uint64_t M[2][9];
+    for (int j = 0; j < 2; ++j) orc_matpow(gen, j, e, nwords, M[j]);
+    apply(g, M, state);
+}
+
+/* Advance n external states, `stride` words apart, by the same e steps. */
+void orc_jump_many(int gen, uint32_t* states, uint64_t n, uint64_t stride, const uint64_t* e,
+                   int nwords) {
+    const orc_gen* g = gen_of(gen);
+    uint64_t M[2][9];
+    for (int j = 0; j < 2; ++j) orc_matpow(gen, j, e, nwords, M[j]);
+    for (uint64_t i = 0; i < n; ++i) apply(g, M, states + i * stride);
 }
 
 /* e = 2^k as little-endian words (k < 64 * 4). */
@@ -288,14 +300,15 @@ enum { ORC_CUR = 0, ORC_START = 6, ORC_SUB = 12, ORC_REC = 18 };
  * Z.  The creator is updated in place.                                      */
 void orc_create_streams(int gen, uint32_t creator[6], uint64_t n, uint32_t* streams) {
     const orc_gen* g = gen_of(gen);
-    uint64_t z[4];
+    uint64_t z[4], M[2][9];
     pow2_words(g->stream_log2, z);
+    for (int j = 0; j < 2; ++j) orc_matpow(gen, j, z, 4, M[j]);  /* A^Z, once */
     for (uint64_t i = 0; i < n; ++i) {
         uint32_t* s = streams + i * ORC_REC;
         memcpy(s + ORC_CUR, creator, 6 * sizeof(uint32_t));
         memcpy(s + ORC_START, creator, 6 * sizeof(uint32_t));
         memcpy(s + ORC_SUB, creator, 6 * sizeof(uint32_t));
-        orc_jump(gen, creator, z, 4);
+        apply(g, M, creator);
     }
 }
 
@@ -304,11 +317,12 @@ void orc_next_substream(int gen, uint32_t* streams, uint64_t n) {
     const orc_gen* g = gen_of(gen);
     uint64_t e[4];
     pow2_words(g->substream_log2, e);
+    orc_jump_many(gen, streams + ORC_SUB, n, ORC_REC, e, 4);
     for (uint64_t i = 0; i < n; ++i) {
         uint32_t* s = streams + i * ORC_REC;
-        orc_jump(gen, s + ORC_SUB, e, 4);
         memcpy(s + ORC_CUR, s + ORC_SUB, 6 * sizeof(uint32_t));
     }
+    (void)g;
 }
 
 void orc_reset_substream(uint32_t* streams, uint64_t n) {
@@ -325,7 +339,7 @@ void orc_reset_stream(uint32_t* streams, uint64_t n) {
 }
 
 void orc_advance(int gen, uint32_t* streams, uint64_t n, uint64_t k) {
-    for (uint64_t i = 0; i < n; ++i) orc_jump(gen, streams + i * ORC_REC + ORC_CUR, &k, 1);
+    orc_jump_many(gen, streams + ORC_CUR, n, ORC_REC, &k, 1);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -1,0 +1,238 @@
+"""Python binding of libmrg355.so (MI355X / gfx950 multi-stream MRG32k3a).
+
+Argument marshalling only: every step runs in the HIP library.  Functions
+carry the C-ABI names (include/mrg355.h); tensors are torch CUDA tensors
+(device memory) or numpy arrays (host memory), passed by pointer.  The HIP
+stream is torch's current stream unless one is given.
+
+Stream records are 18 uint32 words (cur, start, sub); on the torch side they
+are held as int32 tensors of shape (n, 18) and never used for arithmetic.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libmrg355.so")
+
+MRG_GEN_MRG32K3A, MRG_GEN_MRG31K3P = 1, 2
+MRG_UNIFORM, MRG_NORMAL, MRG_EXPONENTIAL, MRG_RAW = 0, 1, 2, 3
+MRG_F64, MRG_F32, MRG_U32 = 0, 1, 2
+MRG_RESET_STREAM, MRG_RESET_SUBSTREAM, MRG_NEXT_SUBSTREAM = 0, 1, 2
+MRG_OK = 0
+STATUS = {0: "MRG_OK", -1: "MRG_E_INVALID_ARG", -2: "MRG_E_INVALID_SEED", -3: "MRG_E_UNSUPPORTED",
+          -4: "MRG_E_HIP", -5: "MRG_E_NOMEM", -6: "MRG_E_CORRUPT_STATE"}
+REC_WORDS = 18
+
+
+class MrgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class mrg_creator(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_uint32 * 6)]
+
+
+class mrg_launch_cfg(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
+                ("nontemporal", ctypes.c_uint32), ("arith", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmrg355.so.  Raises when it has not been built: there is no
+    fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing; build it with "
+                              "`python -m paper_2201_06604_amd.build`")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, sz, u64, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        crp = ctypes.POINTER(mrg_creator)
+        sig = {
+            "mrg_abi_version": (i32, []),
+            "mrg_status_string": (ctypes.c_char_p, [i32]),
+            "mrg_last_error": (ctypes.c_char_p, []),
+            "mrg_seed_check": (i32, [i32, u32p]),
+            "mrg_creator_init": (i32, [i32, crp, u32p]),
+            "mrg_streams_create_host": (i32, [i32, crp, sz, vp]),
+            "mrg_streams_create_device": (i32, [i32, crp, sz, vp, vp]),
+            "mrg_streams_reset": (i32, [i32, vp, sz, i32, vp]),
+            "mrg_streams_advance": (i32, [i32, vp, sz, u64, vp]),
+            "mrg_generate": (i32, [i32, vp, sz, u64, i32, i32, ctypes.c_double, vp, vp]),
+            "mrg_generate_ex": (i32, [i32, vp, sz, u64, i32, i32, ctypes.c_double, vp,
+                                      ctypes.POINTER(mrg_launch_cfg), vp]),
+            "mrg_streams_export_size": (i32, [sz, i32, ctypes.POINTER(sz)]),
+            "mrg_streams_export": (i32, [i32, vp, sz, crp, vp, sz, ctypes.POINTER(sz), vp]),
+            "mrg_streams_import": (i32, [i32, vp, sz, vp, sz, ctypes.POINTER(sz), crp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["mrg_abi_version", "mrg_status_string", "mrg_last_error", "mrg_seed_check",
+            "mrg_creator_init", "mrg_streams_create_host", "mrg_streams_create_device",
+            "mrg_streams_reset", "mrg_streams_advance", "mrg_generate", "mrg_generate_ex",
+            "mrg_streams_export_size", "mrg_streams_export", "mrg_streams_import"]
+
+
+def _check(st):
+    if st != MRG_OK:
+        raise MrgError(st, lib().mrg_last_error().decode())
+    return st
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    """Device pointer of a torch CUDA tensor (or an int address)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return ctypes.c_void_p(t)
+    if not t.is_cuda:
+        raise ValueError("expected a device (CUDA) tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _seed_arr(seed):
+    a = np.ascontiguousarray(np.asarray(seed, dtype=np.uint64).astype(np.uint32))
+    if a.shape != (6,) or not np.array_equal(a.astype(np.uint64), np.asarray(seed, dtype=np.uint64)):
+        raise ValueError("seed must be 6 integers below 2^32")
+    return a
+
+
+# ------------------------------------------------------------------ C names
+def mrg_abi_version():
+    return lib().mrg_abi_version()
+
+
+def mrg_seed_check(seed, gen=MRG_GEN_MRG32K3A):
+    """Returns the status code (0 = valid) without raising."""
+    a = _seed_arr(seed)
+    return lib().mrg_seed_check(gen, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+
+
+def mrg_creator_init(seed, gen=MRG_GEN_MRG32K3A):
+    c = mrg_creator()
+    a = _seed_arr(seed)
+    _check(lib().mrg_creator_init(gen, ctypes.byref(c), a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+    return c
+
+
+def creator_words(c):
+    return np.array(list(c.s), dtype=np.uint32)
+
+
+def mrg_streams_create_host(creator, n, gen=MRG_GEN_MRG32K3A):
+    """n stream records as a host numpy array (n, 18) uint32; `creator` advances."""
+    out = np.zeros((n, REC_WORDS), dtype=np.uint32)
+    _check(lib().mrg_streams_create_host(gen, ctypes.byref(creator), n,
+                                         out.ctypes.data_as(ctypes.c_void_p) if n else None))
+    return out
+
+
+def new_streams_tensor(n, device="cuda"):
+    import torch
+    return torch.empty((n, REC_WORDS), dtype=torch.int32, device=device)
+
+
+def mrg_streams_create_device(creator, n, out=None, gen=MRG_GEN_MRG32K3A, stream=None):
+    """n stream records written by a kernel into `out` (torch int32 (n,18) on
+    the device; allocated when None); `creator` advances."""
+    if out is None:
+        out = new_streams_tensor(max(n, 1))
+    _check(lib().mrg_streams_create_device(gen, ctypes.byref(creator), n, _dptr(out), _stream(stream)))
+    return out
+
+
+def mrg_streams_reset(streams, kind, n=None, gen=MRG_GEN_MRG32K3A, stream=None):
+    n = streams.shape[0] if n is None else n
+    _check(lib().mrg_streams_reset(gen, _dptr(streams), n, kind, _stream(stream)))
+
+
+def mrg_streams_advance(streams, steps, n=None, gen=MRG_GEN_MRG32K3A, stream=None):
+    n = streams.shape[0] if n is None else n
+    _check(lib().mrg_streams_advance(gen, _dptr(streams), n, steps, _stream(stream)))
+
+
+_TORCH_DT = {MRG_F64: "float64", MRG_F32: "float32", MRG_U32: "int32"}
+
+
+def new_output(n, dtype, device="cuda"):
+    import torch
+    return torch.empty(max(n, 1), dtype=getattr(torch, _TORCH_DT[dtype]), device=device)
+
+
+def mrg_generate(streams, n, dist=MRG_UNIFORM, dtype=MRG_F64, param=1.0, out=None,
+                 n_streams=None, cfg=None, gen=MRG_GEN_MRG32K3A, stream=None):
+    """n numbers from the device stream records `streams` into `out`
+    (element k*S + s = draw k of stream s).  U32 results come back in an
+    int32 tensor holding the raw 32-bit words.  `cfg` = dict(block=, chunk=,
+    nontemporal=, arith=) selects a launch shape (results do not change)."""
+    S = streams.shape[0] if n_streams is None else n_streams
+    if out is None:
+        out = new_output(n, dtype)
+    if cfg is None:
+        st = lib().mrg_generate(gen, _dptr(streams), S, n, dist, dtype, param, _dptr(out),
+                                _stream(stream))
+    else:
+        c = mrg_launch_cfg(cfg.get("block", 0), cfg.get("chunk", 0), cfg.get("nontemporal", 0),
+                           cfg.get("arith", 0))
+        st = lib().mrg_generate_ex(gen, _dptr(streams), S, n, dist, dtype, param, _dptr(out),
+                                   ctypes.byref(c), _stream(stream))
+    _check(st)
+    return out
+
+
+def mrg_generate_status(streams_ptr, n_streams, n, dist, dtype, param, out_ptr,
+                        gen=MRG_GEN_MRG32K3A, stream=0):
+    """Raw call returning the status code (for error-path tests)."""
+    return lib().mrg_generate(gen, ctypes.c_void_p(streams_ptr), n_streams, n, dist, dtype, param,
+                              ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream))
+
+
+def mrg_streams_export(streams, n=None, creator=None, gen=MRG_GEN_MRG32K3A, stream=None):
+    """Save n device records (+ creator) into a bytes object."""
+    n = streams.shape[0] if n is None else n
+    need = ctypes.c_size_t()
+    _check(lib().mrg_streams_export_size(n, 1 if creator is not None else 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value)
+    ln = ctypes.c_size_t()
+    _check(lib().mrg_streams_export(gen, _dptr(streams) if n else None, n,
+                                    ctypes.byref(creator) if creator is not None else None,
+                                    buf, need.value, ctypes.byref(ln), _stream(stream)))
+    return buf.raw[:ln.value]
+
+
+def mrg_streams_import(data, out, creator=None, gen=MRG_GEN_MRG32K3A, stream=None):
+    """Restore records from `data` into device tensor `out` (and `creator`).
+    Returns the number of records."""
+    buf = ctypes.create_string_buffer(bytes(data), len(data))
+    cnt = ctypes.c_size_t()
+    _check(lib().mrg_streams_import(gen, buf, len(data), _dptr(out) if out is not None else None,
+                                    out.shape[0] if out is not None else 0, ctypes.byref(cnt),
+                                    ctypes.byref(creator) if creator is not None else None,
+                                    _stream(stream)))
+    return cnt.value
+
+
+def as_u32(t):
+    """Device int32 tensor -> host numpy uint32 (bit reinterpretation)."""
+    return t.detach().cpu().numpy().view(np.uint32)

@@ -1,0 +1,61 @@
+"""Build libmrg355.so (gfx950) in-tree with hipcc.
+
+    python -m paper_2201_06604_amd.build
+"""
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+LIB = os.path.join(PKG, "libmrg355.so")
+SOURCES = ["mrg_kernels.hip", "mrg_api.cpp"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+# Packed-fp32 instructions stay off: hipcc would otherwise form them from
+# ordinary float code.
+HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-fconstexpr-steps=100000000", "-ffp-contract=off",
+             "-Wall", "-Wno-unused-result"]
+
+
+def _compile(src, obj, extra=()):
+    cmd = [HIPCC] + HIP_FLAGS + list(extra) + ["-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                                               "-c", src, "-o", obj]
+    subprocess.run(cmd, check=True, cwd=CSRC)
+
+
+def build(verbose: bool = False) -> str:
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    objs = []
+    for s in SOURCES:
+        src = os.path.join(CSRC, s)
+        obj = os.path.join(objdir, s + ".o")
+        extra = [] if s.endswith(".hip") else ["-x", "hip"]
+        if verbose:
+            print("hipcc", s, flush=True)
+        _compile(src, obj, extra)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs,
+                   check=True, cwd=CSRC)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def disassemble(out_path: str) -> None:
+    """Write the gfx950 assembly of the kernels (for inspection)."""
+    cmd = [HIPCC] + HIP_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                                 "--cuda-device-only", "-S", os.path.join(CSRC, "mrg_kernels.hip"),
+                                 "-o", out_path]
+    subprocess.run(cmd, check=True, cwd=CSRC)
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    if len(sys.argv) > 1 and sys.argv[1] == "--asm":
+        disassemble(sys.argv[2])

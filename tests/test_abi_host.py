@@ -1,0 +1,179 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and its host-side logic (seed rule, creator, host stream
+creation, argument validation, saved-state validation) is right.  Calls that
+would launch a kernel are only made with arguments that fail validation, so
+they return before touching HIP."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads
+from conftest import ROOT
+
+import paper_2201_06604_amd as P
+
+M1, M2 = 4294967087, 4294944443
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+           if f.endswith(".h")]
+
+
+def _declared_functions():
+    names = set()
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"\b(mrg_[a-z0-9_]+)\s*\(", src):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    declared = _declared_functions()
+    assert declared, "no declarations found"
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert set(P.EXPORTED) == declared
+    assert P.mrg_abi_version() == 1
+
+
+def test_status_strings():
+    L = P.lib()
+    for code in P.STATUS:
+        assert L.mrg_status_string(code)
+
+
+def test_seed_rule_matches_oracle():
+    cases = [[12345] * 6, [0, 0, 1, 0, 0, 1], [M1 - 1] * 3 + [M2 - 1] * 3, [M1, 1, 1, 1, 1, 1],
+             [1, 1, 1, M2, 1, 1], [0, 0, 0, 5, 5, 5], [5, 5, 5, 0, 0, 0], [2**32 - 1] * 6]
+    rnd = np.random.default_rng(8)
+    cases += [list(rnd.integers(0, 2**32, size=6)) for _ in range(50)]
+    for c in cases:
+        ok = P.mrg_seed_check(c) == 0
+        assert ok == O.seed_valid(O.MRG32K3A, c), c
+        if not ok:
+            assert P.mrg_seed_check(c) == -2
+
+
+def test_creator_init_rejects_invalid_seed():
+    with pytest.raises(P.MrgError) as e:
+        P.mrg_creator_init([0, 0, 0, 1, 1, 1])
+    assert e.value.status == -2
+    with pytest.raises(P.MrgError) as e:
+        P.mrg_creator_init([1] * 6, gen=7)
+    assert e.value.status == -1
+    with pytest.raises(P.MrgError) as e:
+        P.mrg_creator_init([1] * 6, gen=P.MRG_GEN_MRG31K3P)
+    assert e.value.status == -3
+
+
+@pytest.mark.parametrize("seed", [workloads.PAPER_SEED, list(workloads.random_seed())])
+def test_host_creation_matches_oracle(seed):
+    """createStreamsCpu: records and creator equal the oracle's sequential
+    creation, bit for bit."""
+    c = P.mrg_creator_init(seed)
+    got = P.mrg_streams_create_host(c, 100)
+    oc = np.array(seed, dtype=np.uint32)
+    want = O.create_streams(O.MRG32K3A, oc, 100)
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(P.creator_words(c), oc)
+    # creation continues from the advanced creator
+    got2 = P.mrg_streams_create_host(c, 3)
+    want2 = O.create_streams(O.MRG32K3A, oc, 3)
+    np.testing.assert_array_equal(got2, want2)
+
+
+def test_host_creation_zero_is_noop():
+    c = P.mrg_creator_init([12345] * 6)
+    before = P.creator_words(c).copy()
+    P.mrg_streams_create_host(c, 0)
+    np.testing.assert_array_equal(P.creator_words(c), before)
+
+
+def test_generate_argument_validation_no_side_effects():
+    """Validation failures return before any HIP call (this host has no GPU)."""
+    f = P.mrg_generate_status
+    E = -1
+    # dist/dtype mismatches
+    assert f(256, 4, 10, P.MRG_RAW, P.MRG_F64, 1.0, 256) == E
+    assert f(256, 4, 10, P.MRG_UNIFORM, P.MRG_U32, 1.0, 256) == E
+    assert f(256, 4, 10, P.MRG_NORMAL, P.MRG_U32, 1.0, 256) == E
+    # bad enum values
+    assert f(256, 4, 10, 9, P.MRG_F64, 1.0, 256) == E
+    assert f(256, 4, 10, P.MRG_UNIFORM, 9, 1.0, 256) == E
+    # exponential rate
+    for rate in (0.0, -1.0, float("inf"), float("nan")):
+        assert f(256, 4, 10, P.MRG_EXPONENTIAL, P.MRG_F64, rate, 256) == E
+    # zero streams with n > 0, null pointers, misaligned output
+    assert f(256, 0, 10, P.MRG_UNIFORM, P.MRG_F64, 1.0, 256) == E
+    assert f(0, 4, 10, P.MRG_UNIFORM, P.MRG_F64, 1.0, 256) == E
+    assert f(256, 4, 10, P.MRG_UNIFORM, P.MRG_F64, 1.0, 0) == E
+    assert f(256, 4, 10, P.MRG_UNIFORM, P.MRG_F64, 1.0, 260) == E
+    assert f(256, 4, 10, P.MRG_UNIFORM, P.MRG_F32, 1.0, 258) == E
+    assert f(256, 2**31 + 1, 10, P.MRG_UNIFORM, P.MRG_F64, 1.0, 256) == E
+    # n = 0 is a no-op, even with null pointers
+    assert f(0, 0, 0, P.MRG_UNIFORM, P.MRG_F64, 1.0, 0) == 0
+    # unsupported generator
+    L = P.lib()
+    assert L.mrg_generate(2, ctypes.c_void_p(256), 4, 10, 0, 0, 1.0, ctypes.c_void_p(256), None) == -3
+
+
+def test_launch_cfg_validation():
+    L = P.lib()
+    for cfg in [(100, 0, 0, 0), (256, 0, 2, 0), (256, 0, 0, 3)]:
+        c = P.mrg_launch_cfg(*cfg)
+        st = L.mrg_generate_ex(1, ctypes.c_void_p(256), 4, 10, 0, 0, 1.0, ctypes.c_void_p(256),
+                               ctypes.byref(c), None)
+        assert st == -1, cfg
+
+
+def _saved(n, flags=0, gen=1, version=1, magic=b"MRG3", records=None, creator=None, extra=b""):
+    import struct
+    head = magic + struct.pack("<IIIQ", version, gen, flags, n)
+    body = b"" if records is None else np.ascontiguousarray(records, dtype=np.uint32).tobytes()
+    tail = b"" if creator is None else np.asarray(creator, dtype=np.uint32).tobytes()
+    return head + body + tail + extra
+
+
+def _import_status(data, n_room=8):
+    L = P.lib()
+    buf = ctypes.create_string_buffer(data, len(data))
+    cnt = ctypes.c_size_t()
+    cr = P.mrg_creator()
+    # device pointer 256 is never touched: every case below fails validation
+    return L.mrg_streams_import(1, buf, len(data), ctypes.c_void_p(256), n_room, ctypes.byref(cnt),
+                                ctypes.byref(cr), None)
+
+
+def test_import_rejects_corrupt_buffers():
+    c = P.mrg_creator_init(workloads.random_seed())
+    recs = P.mrg_streams_create_host(c, 3)
+    cre = P.creator_words(c)
+    C = -6
+    assert _import_status(_saved(3, records=recs)[:10]) == C                      # short
+    assert _import_status(_saved(3, records=recs, magic=b"XRG3")) == C            # magic
+    assert _import_status(_saved(3, records=recs, version=2)) == C                # version
+    assert _import_status(_saved(3, records=recs, gen=2)) == C                    # generator
+    assert _import_status(_saved(3, records=recs, flags=4)) == C                  # flags
+    assert _import_status(_saved(3, records=recs, extra=b"\0")) == C              # length
+    assert _import_status(_saved(4, records=recs)) == C                           # count
+    assert _import_status(_saved(3, flags=1, records=recs)) == C                  # missing creator
+    bad = recs.copy()
+    bad[1, 7] = M1                                                                # start word >= m1
+    assert _import_status(_saved(3, records=bad)) == C
+    bad = recs.copy()
+    bad[2, 15:18] = 0                                                             # zero sub triple
+    assert _import_status(_saved(3, records=bad)) == C
+    assert _import_status(_saved(3, flags=1, records=recs, creator=[0, 0, 0, 1, 1, 1])) == C
+    # too little room is reported as such, after validation
+    assert _import_status(_saved(3, flags=1, records=recs, creator=cre), n_room=2) == -5
+
+
+def test_export_size():
+    sz = ctypes.c_size_t()
+    assert P.lib().mrg_streams_export_size(10, 1, ctypes.byref(sz)) == 0
+    assert sz.value == 24 + 10 * 72 + 24

@@ -1,0 +1,291 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+States, uniforms (f64, f32 round-toward-zero) and raw integers must match
+bit for bit.  Normals and exponentials must satisfy
+|gpu - ref| <= tol * max(|ref|, 1) with tol = 1e-15 (f64) and 1e-6 (f32).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2201_06604_amd as P  # noqa: E402
+
+GEN = O.MRG32K3A
+TOL = {P.MRG_F64: 1e-15, P.MRG_F32: 1e-6}
+ODIST = {P.MRG_UNIFORM: O.UNIFORM, P.MRG_NORMAL: O.NORMAL, P.MRG_EXPONENTIAL: O.EXPONENTIAL,
+         P.MRG_RAW: O.RAW}
+ODT = {P.MRG_F64: O.F64, P.MRG_F32: O.F32, P.MRG_U32: O.U32}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+
+
+def dev_streams(host_records):
+    t = torch.from_numpy(host_records.view(np.int32).copy()).cuda()
+    return t
+
+
+def host_out(t, dtype):
+    a = t.cpu().numpy()
+    return a.view(np.uint32) if dtype == P.MRG_U32 else a
+
+
+def check_values(got, want, dist, dtype, ctx=""):
+    if dist in (P.MRG_UNIFORM, P.MRG_RAW):
+        if not np.array_equal(got, want):
+            bad = np.nonzero(got != want)[0]
+            raise AssertionError(f"{ctx}: {bad.size} mismatches, first at {bad[:5]}: "
+                                 f"{got[bad[:5]]} vs {want[bad[:5]]}")
+        return
+    if got.size == 0:
+        assert want.size == 0, ctx
+        return
+    g = got.astype(np.float64)
+    w = want.astype(np.float64)
+    err = np.abs(g - w) / np.maximum(np.abs(w), 1.0)
+    assert np.all(np.isfinite(g)), ctx
+    assert err.max() <= TOL[dtype], f"{ctx}: max rel err {err.max():.3e} at {err.argmax()}"
+
+
+def run_case(records, n, dist, dtype, param=1.0, cfg=None):
+    """Generate on the GPU and with the oracle; compare outputs and states."""
+    S = records.shape[0]
+    d = dev_streams(records)
+    out = P.mrg_generate(d, n, dist, dtype, param, cfg=cfg)
+    torch.cuda.synchronize()
+    work = records.copy()
+    want = O.generate(GEN, work, n, ODIST[dist], ODT[dtype], param, threads=8)
+    got = host_out(out, dtype)[:n]
+    check_values(got, want, dist, dtype, ctx=f"S={S} n={n} dist={dist} dtype={dtype} cfg={cfg}")
+    np.testing.assert_array_equal(P.as_u32(d), work, err_msg=f"states S={S} n={n} cfg={cfg}")
+
+
+# --------------------------------------------------------------- the paper's small config
+def test_plain_small_1024_streams_bit_exact():
+    """Seed 12345 x 6; 1024 streams by 2^127 jumps (device and host creation);
+    1024 fp64 uniforms each: every value and every final state bit-exact."""
+    c_dev = P.mrg_creator_init(workloads.PAPER_SEED)
+    c_host = P.mrg_creator_init(workloads.PAPER_SEED)
+    d = P.mrg_streams_create_device(c_dev, 1024)
+    h = P.mrg_streams_create_host(c_host, 1024)
+    oc = np.array(workloads.PAPER_SEED, dtype=np.uint32)
+    want_rec = O.create_streams(GEN, oc, 1024)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(P.as_u32(d), want_rec)
+    np.testing.assert_array_equal(h, want_rec)
+    np.testing.assert_array_equal(P.creator_words(c_dev), oc)
+    np.testing.assert_array_equal(P.creator_words(c_host), oc)
+    out = P.mrg_generate(d, 1 << 20, P.MRG_UNIFORM, P.MRG_F64)
+    torch.cuda.synchronize()
+    work = want_rec.copy()
+    want = O.generate(GEN, work, 1 << 20, O.UNIFORM, O.F64)
+    got = out.cpu().numpy()
+    assert np.array_equal(got, want)
+    assert got.min() > 0.0 and got.max() < 1.0
+    np.testing.assert_array_equal(P.as_u32(d), work)
+    # the first value is the worked example's u
+    assert got[0] == 545508589 * (1.0 / 4294967088.0)
+
+
+# ------------------------------------------------------ launch shapes and arithmetic
+CFGS = [None,
+        dict(arith=1), dict(arith=2),
+        dict(block=64, chunk=1, arith=1), dict(block=64, chunk=1, arith=2),
+        dict(block=128, chunk=2, arith=1), dict(block=1024, chunk=5, arith=2, nontemporal=1),
+        dict(block=256, chunk=64, arith=1, nontemporal=1), dict(block=512, chunk=7, arith=2),
+        dict(block=256, chunk=100000, arith=1)]
+
+
+@pytest.mark.parametrize("cfg", CFGS, ids=lambda c: str(c))
+def test_schedule_invariance_uniform(cfg):
+    """Every launch shape and both arithmetic forms give the oracle's bits."""
+    rec = O.create_streams(GEN, workloads.random_seed(21), 300)
+    run_case(rec, 300 * 37 + 123, P.MRG_UNIFORM, P.MRG_F64, cfg=cfg)
+
+
+@pytest.mark.parametrize("cfg", [dict(arith=1, chunk=4), dict(arith=2, chunk=3), dict(arith=2, chunk=0)],
+                         ids=str)
+@pytest.mark.parametrize("dist,dtype", [(P.MRG_UNIFORM, P.MRG_F32), (P.MRG_RAW, P.MRG_U32),
+                                        (P.MRG_NORMAL, P.MRG_F64), (P.MRG_NORMAL, P.MRG_F32),
+                                        (P.MRG_EXPONENTIAL, P.MRG_F64),
+                                        (P.MRG_EXPONENTIAL, P.MRG_F32)])
+@pytest.mark.parametrize("S,n", [(77, 77 * 20), (77, 77 * 21 + 5), (130, 130 * 9 + 129), (1, 1001)])
+def test_distributions(cfg, dist, dtype, S, n):
+    rec = O.create_streams(GEN, workloads.random_seed(S + n), S)
+    run_case(rec, n, dist, dtype, 1.0, cfg)
+
+
+@pytest.mark.parametrize("rate", [0.5, 3.0])
+def test_exponential_rate(rate):
+    rec = O.create_streams(GEN, workloads.random_seed(5), 64)
+    run_case(rec, 64 * 50 + 3, P.MRG_EXPONENTIAL, P.MRG_F64, rate)
+
+
+@pytest.mark.parametrize("S,n", [(5, 0), (100, 7), (100, 99), (64, 64), (65, 1), (1, 3)])
+def test_edges(S, n):
+    """Empty calls, fewer numbers than streams, single streams."""
+    rec = O.create_streams(GEN, workloads.random_seed(9), S)
+    for dist, dtype in [(P.MRG_UNIFORM, P.MRG_F64), (P.MRG_NORMAL, P.MRG_F64)]:
+        run_case(rec, n, dist, dtype)
+
+
+def test_arbitrary_states_not_stream_starts():
+    """States far from stream starts (random valid words)."""
+    st = workloads.random_states(200, 77)
+    rec = np.zeros((200, 18), dtype=np.uint32)
+    rec[:, 0:6] = st
+    rec[:, 6:12] = st
+    rec[:, 12:18] = st
+    run_case(rec, 200 * 33 + 17, P.MRG_UNIFORM, P.MRG_F64, cfg=dict(arith=1, chunk=8))
+    run_case(rec, 200 * 33 + 17, P.MRG_UNIFORM, P.MRG_F64, cfg=dict(arith=2, chunk=8))
+    run_case(rec, 200 * 33 + 17, P.MRG_RAW, P.MRG_U32, cfg=dict(arith=2))
+
+
+def test_extreme_states():
+    """Words at the top of their ranges, and the z = m1 output (x1 == x2)."""
+    M1, M2 = 4294967087, 4294944443
+    st = np.array([[M1 - 1, M1 - 1, M1 - 1, M2 - 1, M2 - 1, M2 - 1],
+                   [1, 0, 0, 1, 0, 0],
+                   [0, 0, 1, 0, 0, 1],
+                   [M1 - 1, 0, M1 - 1, 0, M2 - 1, 0],
+                   [5, 5, 5, 5, 5, 5]], dtype=np.uint32)
+    rec = np.concatenate([st, st, st], axis=1)
+    for cfg in (dict(arith=1), dict(arith=2)):
+        run_case(rec, 5 * 40, P.MRG_RAW, P.MRG_U32, cfg=cfg)
+        run_case(rec, 5 * 40, P.MRG_UNIFORM, P.MRG_F32, cfg=cfg)
+
+
+def test_many_chunks_one_stream():
+    """One long stream split over many work-items (chunk jumps of many bits)."""
+    rec = O.create_streams(GEN, workloads.random_seed(4), 1)
+    run_case(rec, 200003, P.MRG_UNIFORM, P.MRG_F64, cfg=dict(chunk=777, arith=1))
+    run_case(rec, 200003, P.MRG_NORMAL, P.MRG_F64, cfg=dict(chunk=333, arith=2))
+
+
+# ------------------------------------------------------------ streams API
+def test_device_creation_equals_host_creation_large():
+    seed = workloads.random_seed()
+    c1, c2 = P.mrg_creator_init(seed), P.mrg_creator_init(seed)
+    d = P.mrg_streams_create_device(c1, 70001)
+    h = P.mrg_streams_create_host(c2, 70001)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(P.as_u32(d), h)
+    np.testing.assert_array_equal(P.creator_words(c1), P.creator_words(c2))
+    oc = seed.copy()
+    want = O.create_streams(GEN, oc, 70001)
+    np.testing.assert_array_equal(h, want)
+    np.testing.assert_array_equal(P.creator_words(c1), oc)
+
+
+def test_substreams_and_advance():
+    seed = workloads.random_seed(12)
+    rec = O.create_streams(GEN, seed.copy(), 129)
+    d = dev_streams(rec)
+    work = rec.copy()
+    P.mrg_streams_advance(d, 123456789012345)
+    O.advance(GEN, work, 123456789012345)
+    P.mrg_streams_reset(d, P.MRG_NEXT_SUBSTREAM)
+    O.next_substream(GEN, work)
+    P.mrg_streams_advance(d, 2**64 - 1)
+    O.advance(GEN, work, 2**64 - 1)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(P.as_u32(d), work)
+    P.mrg_streams_reset(d, P.MRG_RESET_SUBSTREAM)
+    O.reset_substream(work)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(P.as_u32(d), work)
+    P.mrg_streams_reset(d, P.MRG_NEXT_SUBSTREAM)
+    P.mrg_streams_reset(d, P.MRG_NEXT_SUBSTREAM)
+    O.next_substream(GEN, work)
+    O.next_substream(GEN, work)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(P.as_u32(d), work)
+    P.mrg_streams_reset(d, P.MRG_RESET_STREAM)
+    O.reset_stream(work)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(P.as_u32(d), work)
+
+
+def test_export_import_roundtrip_continues_identically():
+    """Save/restore (saveRDS/readRDS example): generation continued from a
+    restored copy equals uninterrupted generation."""
+    c = P.mrg_creator_init(workloads.random_seed(31))
+    d = P.mrg_streams_create_device(c, 500)
+    P.mrg_generate(d, 500 * 11 + 7, P.MRG_NORMAL, P.MRG_F64)
+    blob = P.mrg_streams_export(d, creator=c)
+    d2 = P.new_streams_tensor(500)
+    c2 = P.mrg_creator()
+    assert P.mrg_streams_import(blob, d2, creator=c2) == 500
+    np.testing.assert_array_equal(P.creator_words(c2), P.creator_words(c))
+    a = P.mrg_generate(d, 500 * 20, P.MRG_UNIFORM, P.MRG_F64)
+    b = P.mrg_generate(d2, 500 * 20, P.MRG_UNIFORM, P.MRG_F64)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    np.testing.assert_array_equal(P.as_u32(d), P.as_u32(d2))
+    # new streams from the restored creator continue the same sequence
+    e1 = P.mrg_streams_create_device(c, 3)
+    e2 = P.mrg_streams_create_device(c2, 3)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(P.as_u32(e1), P.as_u32(e2))
+
+
+def test_reproducible_by_creation_order():
+    """Same creator seed and creation order give identical numbers (Section 2.2
+    reproducibility loop)."""
+    def program():
+        c = P.mrg_creator_init([11, 22, 33, 44, 55, 66])
+        rows = []
+        for i in range(1, 11):
+            if i % 2 == 0:
+                s = P.mrg_streams_create_device(c, 4)
+                rows.append(P.mrg_generate(s, 6, P.MRG_NORMAL, P.MRG_F64).cpu().numpy()[:6])
+            elif i == 3:
+                s = P.mrg_streams_create_device(c, 4)
+                rows.append(P.mrg_generate(s, 6, P.MRG_UNIFORM, P.MRG_F64).cpu().numpy()[:6])
+            else:
+                s = P.mrg_streams_create_device(c, 8)
+                rows.append(P.mrg_generate(s, 6, P.MRG_EXPONENTIAL, P.MRG_F64).cpu().numpy()[:6])
+        return np.array(rows)
+    a, b = program(), program()
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------ full size
+def test_throughput_config_full_size_sampled():
+    """262,144 streams x 4096 fp64 uniforms (2^30) in the launch shape the
+    benchmark times: every final state, 4096 random streams in full, and the
+    first 16 draws of every stream, bit-exact."""
+    S, per = 262144, 4096
+    seed = workloads.random_seed()
+    c = P.mrg_creator_init(seed)
+    d = P.mrg_streams_create_device(c, S)
+    oc = seed.copy()
+    rec = O.create_streams(GEN, oc, S)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(P.as_u32(d), rec)
+    out = P.mrg_generate(d, S * per, P.MRG_UNIFORM, P.MRG_F64)
+    torch.cuda.synchronize()
+    fin = rec[:, 0:6].copy()
+    O.jump_many(GEN, fin, per)
+    np.testing.assert_array_equal(P.as_u32(d)[:, 0:6], fin)
+    np.testing.assert_array_equal(P.as_u32(d)[:, 6:18], rec[:, 6:18])
+    mat = out.view(per, S)
+    head = mat[:16].cpu().numpy()
+    want_head = O.generate(GEN, rec.copy(), 16 * S, threads=8).reshape(16, S)
+    assert np.array_equal(head, want_head)
+    rnd = np.random.default_rng(3)
+    idx = np.sort(rnd.choice(S, size=4096, replace=False))
+    cols = mat[:, torch.from_numpy(idx).cuda()].cpu().numpy()
+    sub = rec[idx].copy()
+    want_cols = O.generate(GEN, sub, per * 4096, threads=8).reshape(per, 4096)
+    assert np.array_equal(cols, want_cols)
+    del out
