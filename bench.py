@@ -1,0 +1,179 @@
+"""Benchmark: MRG32k3a multi-stream generation on one MI355X.
+
+One step = create 262,144 streams on the device from a seeded random 6-word
+seed (2^127 jump-ahead) + generate 2^30 fp64 uniforms from them (4,096 per
+stream, element k*S + s = draw k of stream s) + the state write-back.
+Inputs and outputs stay in HBM.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--copy-probe]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+S_STREAMS = 262144
+PER_STREAM = 4096
+N = S_STREAMS * PER_STREAM
+HBM_PEAK_GBPS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
+    ap.add_argument("--no-variants", action="store_true", help="skip f32/normal/exponential timings")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--traffic", type=str, default=None,
+                    help="JSON file with measured HBM traffic per launch (bytes)")
+    return ap.parse_args()
+
+
+def cpu_baseline(seed):
+    """The oracle, as it is, on the host cores: 65,536 of the streams x 4,096
+    fp64 uniforms (2^28 draws), split over threads."""
+    import oracle as O
+    threads = max(1, min(16, os.cpu_count() or 1))
+    S_sample = 65536
+    c = seed.copy()
+    rec = O.create_streams(O.MRG32K3A, c, S_sample)
+    n = S_sample * PER_STREAM
+    t0 = time.perf_counter()
+    O.generate(O.MRG32K3A, rec, n, O.UNIFORM, O.F64, 1.0, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt / 1e9, "unit": "GSamples/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {S_sample} of the {S_STREAMS} streams x {PER_STREAM} fp64 uniforms "
+                      f"({n} draws, {dt:.2f} s wall on {threads} threads)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+              "(streams shard by block across GPUs with no exchange; see the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2201_06604_amd as P
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    seed = workloads.random_seed()
+    streams = P.new_streams_tensor(S_STREAMS)
+    out = torch.empty(N, dtype=torch.float64, device=dev)
+
+    def step():
+        c = P.mrg_creator_init(seed)
+        P.mrg_streams_create_device(c, S_STREAMS, out=streams)
+        P.mrg_generate(streams, N, P.MRG_UNIFORM, P.MRG_F64, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K whole steps; the generate launch is bracketed by events
+    # on the stream it runs on (torch's current stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        c = P.mrg_creator_init(seed)
+        P.mrg_streams_create_device(c, S_STREAMS, out=streams)
+        ev[i][0].record()
+        P.mrg_generate(streams, N, P.MRG_UNIFORM, P.MRG_F64, out=out)
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gen_ms = [a.elapsed_time(b) for a, b in ev]
+    ms_per_step = wall * 1e3 / args.steps
+    value = N / (ms_per_step * 1e-3) / 1e9
+    gen_avg_ms = float(np.mean(gen_ms))
+    alg_bytes = N * 8 + S_STREAMS * 48  # output + state read and written
+    achieved = alg_bytes / (gen_avg_ms * 1e-3) / 1e9
+
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            traffic = json.load(f).get("bytes_per_launch")
+
+    res = {
+        "metric": "GSamples/s MRG32k3a fp64 uniforms (bit-exact); p99 latency, batched vs plain",
+        "value": round(value, 3),
+        "unit": "GSamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "MRG32k3a: 262,144 streams created on device by 2^127 jump-ahead "
+                               "from a seeded random 6-word seed, 4,096 fp64 uniforms each "
+                               "(2^30 per step), interleaved output k*S+s",
+                   "streams": S_STREAMS, "per_stream": PER_STREAM, "dist": "uniform",
+                   "out_dtype": "f64"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic,
+                     "kernel": "gen_kernel<uniform,f64>", "alg_bytes_per_launch": alg_bytes,
+                     "avg_launch_ms": round(gen_avg_ms, 4)},
+    }
+
+    # store-only ceiling: torch's fill of the same 8 GiB buffer
+    fe = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    out.fill_(0.5)
+    fe[0].record()
+    for _ in range(5):
+        out.fill_(0.5)
+    fe[1].record()
+    torch.cuda.synchronize()
+    fill_ms = fe[0].elapsed_time(fe[1]) / 5
+    res["store_only_fill_GBps"] = round(N * 8 / (fill_ms * 1e-3) / 1e9, 1)
+
+    if not args.no_variants:
+        var = {}
+        out32 = torch.empty(N, dtype=torch.float32, device=dev)
+        for name, dist, dt, o, esz in [("f32_uniform", P.MRG_UNIFORM, P.MRG_F32, out32, 4),
+                                       ("f64_normal", P.MRG_NORMAL, P.MRG_F64, out, 8),
+                                       ("f64_exponential", P.MRG_EXPONENTIAL, P.MRG_F64, out, 8)]:
+            P.mrg_generate(streams, N, dist, dt, 1.0, out=o)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(3):
+                P.mrg_generate(streams, N, dist, dt, 1.0, out=o)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / 3
+            var[name] = {"GSamples_per_s": round(N / (ms * 1e-3) / 1e9, 2),
+                         "GB_per_s": round(N * esz / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4)}
+        del out32
+        res["variants"] = var
+
+    if args.copy_probe:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        res["copy_probe_bytes"] = a.numel() * 8
+
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(seed)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
