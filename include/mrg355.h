@@ -90,16 +90,23 @@ typedef enum {
 
 /* Launch shape of mrg_generate_ex.  Results never depend on it: the output
  * position and every value are functions of (stream, draw index) only.
- *   block      threads per block: 64, 128, 256, 512 or 1024
- *   chunk      draws (normal: pairs) per work-item, >= 1; 0 = automatic
- *   nontemporal 1 = stream the output with non-temporal stores
- *   arith      0 = automatic, 1 = 32x32->64 integer mod arithmetic,
- *              2 = the same integers carried exactly in fp64 FMA registers */
+ *   block            threads per block: 0 (automatic), 64, 128, 256, 512, 1024
+ *   chunk            draws (normal: pairs) per work-item; 0 = automatic
+ *   nontemporal      1 = stream the output with non-temporal stores
+ *   arith            0 = automatic, 1 = 32x32->64 integer mod arithmetic,
+ *                    2 = the same integers carried exactly in fp64 FMA registers
+ *   streams_per_lane 0 = automatic, 1, 2 or 4: a request; the value used is
+ *                    the largest not above it that keeps a store within 16
+ *                    bytes and divides n_streams, with the output aligned to
+ *                    the store width
+ *   xcd_remap        1 = give each XCD a contiguous range of row segments   */
 typedef struct {
     uint32_t block;
     uint32_t chunk;
     uint32_t nontemporal;
     uint32_t arith;
+    uint32_t streams_per_lane;
+    uint32_t xcd_remap;
 } mrg_launch_cfg;
 
 int         mrg_abi_version(void);

@@ -38,7 +38,19 @@ class mrg_creator(ctypes.Structure):
 
 class mrg_launch_cfg(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
-                ("nontemporal", ctypes.c_uint32), ("arith", ctypes.c_uint32)]
+                ("nontemporal", ctypes.c_uint32), ("arith", ctypes.c_uint32),
+                ("streams_per_lane", ctypes.c_uint32), ("xcd_remap", ctypes.c_uint32)]
+
+
+CFG_KEYS = ("block", "chunk", "nontemporal", "arith", "streams_per_lane", "xcd_remap")
+
+
+def launch_cfg(cfg):
+    """dict -> mrg_launch_cfg (missing keys are 0 = automatic)."""
+    unknown = set(cfg) - set(CFG_KEYS)
+    if unknown:
+        raise ValueError(f"unknown launch keys {sorted(unknown)}")
+    return mrg_launch_cfg(*[int(cfg.get(k, 0)) for k in CFG_KEYS])
 
 
 _lib = None
@@ -184,8 +196,8 @@ def mrg_generate(streams, n, dist=MRG_UNIFORM, dtype=MRG_F64, param=1.0, out=Non
                  n_streams=None, cfg=None, gen=MRG_GEN_MRG32K3A, stream=None):
     """n numbers from the device stream records `streams` into `out`
     (element k*S + s = draw k of stream s).  U32 results come back in an
-    int32 tensor holding the raw 32-bit words.  `cfg` = dict(block=, chunk=,
-    nontemporal=, arith=) selects a launch shape (results do not change)."""
+    int32 tensor holding the raw 32-bit words.  `cfg` = dict with keys of
+    CFG_KEYS selects a launch shape (results do not change)."""
     S = streams.shape[0] if n_streams is None else n_streams
     if out is None:
         out = new_output(n, dtype)
@@ -193,8 +205,7 @@ def mrg_generate(streams, n, dist=MRG_UNIFORM, dtype=MRG_F64, param=1.0, out=Non
         st = lib().mrg_generate(gen, _dptr(streams), S, n, dist, dtype, param, _dptr(out),
                                 _stream(stream))
     else:
-        c = mrg_launch_cfg(cfg.get("block", 0), cfg.get("chunk", 0), cfg.get("nontemporal", 0),
-                           cfg.get("arith", 0))
+        c = launch_cfg(cfg)
         st = lib().mrg_generate_ex(gen, _dptr(streams), S, n, dist, dtype, param, _dptr(out),
                                    ctypes.byref(c), _stream(stream))
     _check(st)

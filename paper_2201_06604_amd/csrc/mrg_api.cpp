@@ -178,10 +178,16 @@ mrg_status mrg_generate_ex(mrg_generator gen, mrg_stream* dev, size_t n_streams,
             return fail(MRG_E_INVALID_ARG, "block must be 64, 128, 256, 512 or 1024");
         if (cfg->arith > 2) return fail(MRG_E_INVALID_ARG, "arith must be 0, 1 or 2");
         if (cfg->nontemporal > 1) return fail(MRG_E_INVALID_ARG, "nontemporal must be 0 or 1");
+        uint32_t spl = cfg->streams_per_lane;
+        if (spl != 0 && spl != 1 && spl != 2 && spl != 4)
+            return fail(MRG_E_INVALID_ARG, "streams_per_lane must be 0, 1, 2 or 4");
+        if (cfg->xcd_remap > 1) return fail(MRG_E_INVALID_ARG, "xcd_remap must be 0 or 1");
         L.block = static_cast<int>(b);
         L.chunk = cfg->chunk;
         L.nontemporal = static_cast<int>(cfg->nontemporal);
         L.arith = static_cast<int>(cfg->arith);
+        L.spl = static_cast<int>(spl);
+        L.xcd = static_cast<int>(cfg->xcd_remap);
     }
     if (n == 0) return ok();
     if (n_streams == 0) return fail(MRG_E_INVALID_ARG, "n_streams is 0 with n > 0");

@@ -22,6 +22,8 @@ struct GenLaunch {
     uint32_t n_chunks;   // work-items per stream
     double param;        // 1/rate for exponentials
     int dist, dtype, arith, block, nontemporal;
+    int spl;             // streams per lane (1, 2, 4); 0 = automatic
+    int xcd;             // 1 = XCD-contiguous block order
 };
 
 // Resolve chunk/n_chunks/block/arith left at 0 to the automatic choice.

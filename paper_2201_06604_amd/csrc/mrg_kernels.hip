@@ -106,14 +106,23 @@ constexpr double kM2d = static_cast<double>(kM2);
 constexpr double kInvM1 = 1.0 / kM1d;
 constexpr double kInvM2 = 1.0 / kM2d;
 
-// p an integer with |p| < 2^53 -> p mod m in [0, m), exactly.
-__device__ __forceinline__ double f64_mod(double p, double m, double inv_m) {
-    double q = __builtin_rint(p * inv_m);       // nearest quotient (off by <= 1)
-    double r = __builtin_fma(-q, m, p);         // exact, |r| <= m/2 + 4
-    double t = __builtin_floor(r * inv_m);      // -1 or 0
-    return __builtin_fma(-t, m, r);             // exact, in [0, m)
+// p an integer with |p| < 2^53 -> an integer r = p (mod m) with
+// |r| <= m/2 + 4, exactly: q is the nearest quotient (off by at most one),
+// and p - q*m is exact in one FMA.
+__device__ __forceinline__ double f64_rem(double p, double m, double inv_m) {
+    double q = __builtin_rint(p * inv_m);
+    return __builtin_fma(-q, m, p);
 }
 
+// |r| <= m/2 + 4 -> r mod m in [0, m): floor(r/m) is -1 or 0.
+__device__ __forceinline__ double f64_canon(double r, double m, double inv_m) {
+    double t = __builtin_floor(r * inv_m);
+    return __builtin_fma(-t, m, r);
+}
+
+// Component 1 is carried as any residue with |x| <= m1/2 + 4 (its value only
+// matters mod m1); component 2 is kept in [0, m2) because z uses its value.
+// Products stay below 2^53 in magnitude either way, so every FMA is exact.
 struct F64Engine {
     double a0, a1, a2, b0, b1, b2;
 
@@ -121,19 +130,23 @@ struct F64Engine {
         a0 = x[0]; a1 = x[1]; a2 = x[2]; b0 = x[3]; b1 = x[4]; b2 = x[5];
     }
     __device__ __forceinline__ void save(uint32_t x[6]) const {
-        x[0] = static_cast<uint32_t>(a0); x[1] = static_cast<uint32_t>(a1);
-        x[2] = static_cast<uint32_t>(a2); x[3] = static_cast<uint32_t>(b0);
-        x[4] = static_cast<uint32_t>(b1); x[5] = static_cast<uint32_t>(b2);
+        x[0] = static_cast<uint32_t>(f64_canon(a0, kM1d, kInvM1));
+        x[1] = static_cast<uint32_t>(f64_canon(a1, kM1d, kInvM1));
+        x[2] = static_cast<uint32_t>(f64_canon(a2, kM1d, kInvM1));
+        x[3] = static_cast<uint32_t>(b0); x[4] = static_cast<uint32_t>(b1);
+        x[5] = static_cast<uint32_t>(b2);
     }
     static __device__ __forceinline__ double kernel(double& o1, double m2_1, double& o2, double n1_2) {
-        // a12 x - a13n y and a21 x - a23n y are exact: every term < 2^53.
         double p1 = __builtin_fma(static_cast<double>(kA12), m2_1, -(static_cast<double>(kA13N) * o1));
         double p2 = __builtin_fma(static_cast<double>(kA21), n1_2, -(static_cast<double>(kA23N) * o2));
-        double x1 = f64_mod(p1, kM1d, kInvM1), x2 = f64_mod(p2, kM2d, kInvM2);
+        double x1 = f64_rem(p1, kM1d, kInvM1);
+        double x2 = f64_canon(f64_rem(p2, kM2d, kInvM2), kM2d, kInvM2);
         o1 = x1;
         o2 = x2;
-        // z = d if d >= 1 else d + m1, d = x1 - x2 in [-(m2-1), m1-1]:
-        // floor((d-1)/m1) is -1 or 0 and is computed exactly enough here.
+        // z = d mod m1 in [1, m1], d = x1 - x2 in [-(1.5 m1 + 4), m1/2 + 4]:
+        // t = floor((d-1)/m1) in {-2, -1, 0}.  Near a multiple of m1 the
+        // quotient differs from it by at least 1/m1, far above the rounding
+        // of the FMA, so t is exact.
         double d = x1 - x2;
         double t = __builtin_floor(__builtin_fma(d, kInvM1, -kInvM1));
         return __builtin_fma(-t, kM1d, d);
@@ -166,27 +179,26 @@ __device__ __forceinline__ float f32_rz(double u) {
     return __uint_as_float(static_cast<uint32_t>(r >> 29));
 }
 
-template <typename T, bool NT>
-__device__ __forceinline__ void put(T* p, T v) {
-    if (NT) __builtin_nontemporal_store(v, p);
-    else *p = v;
-}
+template <int DTYPE> struct ElemOf;
+template <> struct ElemOf<kF64> { using T = double; };
+template <> struct ElemOf<kF32> { using T = float; };
+template <> struct ElemOf<kU32> { using T = uint32_t; };
 
-// Store one uniform / raw / exponential draw with value from z.
-template <int DIST, int DTYPE, bool NT, typename Z>
-__device__ __forceinline__ void emit1(void* row, int lane, Z z, double inv_rate) {
-    if (DIST == kRaw) {
-        put<uint32_t, NT>(static_cast<uint32_t*>(row) + lane, to_u32(z));
-        return;
-    }
-    double u = to_f64(z) * kNorm;
-    double v = u;
-    if (DIST == kExponential) v = -log(u) * inv_rate;
-    if (DTYPE == kF64) {
-        put<double, NT>(static_cast<double*>(row) + lane, v);
+// The stored value of one uniform / raw / exponential draw.
+template <int DIST, int DTYPE, typename Z>
+__device__ __forceinline__ typename ElemOf<DTYPE>::T value1(Z z, double inv_rate) {
+    if constexpr (DIST == kRaw) {
+        return to_u32(z);
     } else {
-        float f = DIST == kUniform ? f32_rz(u) : static_cast<float>(v);
-        put<float, NT>(static_cast<float*>(row) + lane, f);
+        double u = to_f64(z) * kNorm;
+        if constexpr (DIST == kExponential) {
+            double v = -log(u) * inv_rate;
+            if constexpr (DTYPE == kF64) return v;
+            else return static_cast<float>(v);
+        } else {
+            if constexpr (DTYPE == kF64) return u;
+            else return f32_rz(u);
+        }
     }
 }
 
@@ -201,112 +213,211 @@ __device__ __forceinline__ void box_muller(Z z1, Z z2, double& x, double& y) {
     y = r * s;
 }
 
-template <int DTYPE, bool NT>
-__device__ __forceinline__ void emit_val(void* row, int lane, double v) {
-    if (DTYPE == kF64) put<double, NT>(static_cast<double*>(row) + lane, v);
-    else put<float, NT>(static_cast<float*>(row) + lane, static_cast<float>(v));
+template <int DTYPE>
+__device__ __forceinline__ typename ElemOf<DTYPE>::T narrow(double v) {
+    if constexpr (DTYPE == kF64) return v;
+    else return static_cast<float>(v);
 }
 
-template <int DTYPE>
-__device__ __forceinline__ char* advance_row(char* row, uint64_t S) {
-    return row + S * (DTYPE == kF64 ? 8 : 4);
+// ------------------------------------------------------------ row stores
+// A row is the segment of one draw index that a wave writes: 64*SPL
+// consecutive elements.  Stores go through a buffer resource whose base is
+// the (wave-uniform, SGPR) row address and whose size is the rest of the row,
+// so the per-lane offset is one fixed VGPR and no 64-bit address arithmetic
+// runs per store.  An access past the row end would be dropped by hardware.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int N>
+struct Pack {
+    T v[N];
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const char* row, uint32_t bytes) {
+    // 0x00020000: 32-bit data format, as untyped buffer access expects on gfx9.
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(row), 0, static_cast<int>(bytes),
+                                             0x00020000);
+}
+
+template <typename T, int N, bool NT>
+__device__ __forceinline__ void store_n(__amdgpu_buffer_rsrc_t r, uint32_t voff, const Pack<T, N>& p) {
+    constexpr int kAux = NT ? 2 : 0;  // nt bit
+    constexpr int kBytes = N * static_cast<int>(sizeof(T));
+    static_assert(kBytes == 4 || kBytes == 8 || kBytes == 16, "store width");
+    if constexpr (kBytes == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, p), r, voff, 0, kAux);
+    } else if constexpr (kBytes == 8) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, p), r, voff, 0, kAux);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, p), r, voff, 0, kAux);
+    }
+}
+
+template <typename T, bool NT>
+__device__ __forceinline__ void store_1(__amdgpu_buffer_rsrc_t r, uint32_t voff, T v) {
+    Pack<T, 1> p{{v}};
+    store_n<T, 1, NT>(r, voff, p);
 }
 
 // ------------------------------------------------------------ generate
-template <int DIST, int DTYPE, int ARITH, bool NT>
+// One wave = 64 lanes x SPL consecutive streams, one chunk of draw indices.
+// Lane l owns streams s0 .. s0+SPL-1, s0 = first + l*SPL, and stores their
+// SPL values of a draw index with one SPL*esz-byte store.
+template <int DIST, int DTYPE, int ARITH, int SPL, bool NT>
 __global__ void __launch_bounds__(1024) gen_kernel(GenLaunch L) {
     using Engine = typename std::conditional<ARITH == kArithF64, F64Engine, IntEngine>::type;
-    constexpr int ESZ = DTYPE == kF64 ? 8 : 4;
-    const int lane = threadIdx.x & 63;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t sblk = blockIdx.x * (blockDim.x >> 6) + wave;
-    const uint32_t n_sblk = (L.S + 63) >> 6;
-    if (sblk >= n_sblk) return;
-    const uint32_t s = sblk * 64 + lane;
-    if (s >= L.S) return;
-
-    // Work is counted in units: draws, or Box-Muller pairs for normals.
-    const uint64_t cnt = L.q + (s < L.r ? 1 : 0);
-    const uint64_t cnt_max = L.q + (L.r ? 1 : 0);
-    const uint64_t units = DIST == kNormal ? (cnt + 1) / 2 : cnt;
-    const uint64_t units_max = DIST == kNormal ? (cnt_max + 1) / 2 : cnt_max;
-    const uint64_t full = DIST == kNormal ? L.q / 2 : L.q;  // units every stream completes
-    const uint64_t u0 = static_cast<uint64_t>(blockIdx.y) * L.chunk;
-    if (u0 >= units) return;
-    const uint64_t u1 = min(u0 + L.chunk, units_max);
+    using T = typename ElemOf<DTYPE>::T;
+    constexpr uint32_t ESZ = sizeof(T);
+    constexpr uint32_t WS = 64 * SPL;                   // streams per wave
     constexpr uint64_t kSpu = DIST == kNormal ? 2 : 1;  // steps per unit
 
-    uint32_t* rec = L.streams + static_cast<uint64_t>(s) * 18;
-    uint32_t x[6];
+    // Block -> (stream block, chunk).  With xcd remapping, consecutive logical
+    // blocks (neighbouring row segments) land on one XCD, whose L2 then sees
+    // contiguous runs of every row; blocks are dealt to the 8 XCDs in turn.
+    uint32_t bx = blockIdx.x, by = blockIdx.y;
+    if (L.xcd) {
+        const uint32_t total = gridDim.x * gridDim.y;
+        uint32_t lin = blockIdx.x + blockIdx.y * gridDim.x;
+        lin = (lin % 8) * (total / 8) + lin / 8;  // host guarantees total % 8 == 0
+        bx = lin % gridDim.x;
+        by = lin / gridDim.x;
+    }
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t sblk = bx * (blockDim.x >> 6) + wave;
+    const uint32_t S = L.S;
+    const uint32_t n_sblk = (S + WS - 1) / WS;
+    if (sblk >= n_sblk) return;
+    const uint32_t first = sblk * WS;
+    const uint32_t s0 = first + lane * SPL;
+    if (s0 >= S) return;  // S % SPL == 0: a lane's streams are all present or all absent
+
+    // Work is counted in units: draws, or Box-Muller pairs for normals.
+    uint64_t cnt[SPL], units[SPL];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) x[i] = rec[i];
-    if (u0) dev_jump(x, u0 * kSpu);
-    Engine e;
-    e.load(x);
+    for (int i = 0; i < SPL; ++i) {
+        cnt[i] = L.q + (s0 + i < L.r ? 1 : 0);
+        units[i] = DIST == kNormal ? (cnt[i] + 1) / 2 : cnt[i];
+    }
+    const uint64_t cnt_max = L.q + (L.r ? 1 : 0);
+    const uint64_t units_max = DIST == kNormal ? (cnt_max + 1) / 2 : cnt_max;
+    const uint64_t full = DIST == kNormal ? L.q / 2 : L.q;  // units every stream completes
+    const uint64_t u0 = static_cast<uint64_t>(by) * L.chunk;
+    if (u0 >= units[0]) return;  // counts do not increase with s: stream s0 has the most
+    const uint64_t u1 = min(u0 + L.chunk, units_max);
+
+    Engine e[SPL];
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) {
+        const uint32_t* rec = L.streams + static_cast<uint64_t>(s0 + i) * 18;
+        uint32_t x[6];
+#pragma unroll
+        for (int w = 0; w < 6; ++w) x[w] = rec[w];
+        if (u0) dev_jump(x, u0 * kSpu);
+        e[i].load(x);
+    }
 
     const double inv_rate = L.param;
-    const uint64_t S = L.S;
+    const uint64_t rowstep = static_cast<uint64_t>(S) * ESZ;
+    const uint64_t rest = static_cast<uint64_t>(S - first) * ESZ;
+    const uint32_t nrec = rest > 0xffffffffull ? 0xffffffffu : static_cast<uint32_t>(rest);
+    const uint32_t voff = lane * SPL * ESZ;
+    const char* row = static_cast<const char*>(L.out) + (u0 * kSpu * S + first) * ESZ;
     const uint64_t kend = max(u0, min(u1, full));
     uint64_t k = u0;
-    // Uniform row pointer: first draw of this chunk, first stream of the wave.
-    char* row = static_cast<char*>(L.out) + (k * kSpu * S + static_cast<uint64_t>(sblk) * 64) * ESZ;
 
-    if (DIST == kNormal) {
+    if constexpr (DIST == kNormal) {
+        // 3 pairs = 6 steps per iteration: the register ring returns home.
         for (; k + 3 <= kend; k += 3) {
-            double x0, y0, x1v, y1v, x2v, y2v;
-            auto z0 = e.template step<0>();
-            auto z1 = e.template step<1>();
-            auto z2 = e.template step<2>();
-            auto z3 = e.template step<0>();
-            auto z4 = e.template step<1>();
-            auto z5 = e.template step<2>();
-            box_muller(z0, z1, x0, y0);
-            box_muller(z2, z3, x1v, y1v);
-            box_muller(z4, z5, x2v, y2v);
-            emit_val<DTYPE, NT>(row, lane, x0); row = advance_row<DTYPE>(row, S);
-            emit_val<DTYPE, NT>(row, lane, y0); row = advance_row<DTYPE>(row, S);
-            emit_val<DTYPE, NT>(row, lane, x1v); row = advance_row<DTYPE>(row, S);
-            emit_val<DTYPE, NT>(row, lane, y1v); row = advance_row<DTYPE>(row, S);
-            emit_val<DTYPE, NT>(row, lane, x2v); row = advance_row<DTYPE>(row, S);
-            emit_val<DTYPE, NT>(row, lane, y2v); row = advance_row<DTYPE>(row, S);
+            Pack<T, SPL> px[3], py[3];
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                auto z0 = e[i].template step<0>();
+                auto z1 = e[i].template step<1>();
+                auto z2 = e[i].template step<2>();
+                auto z3 = e[i].template step<0>();
+                auto z4 = e[i].template step<1>();
+                auto z5 = e[i].template step<2>();
+                double x, y;
+                box_muller(z0, z1, x, y);
+                px[0].v[i] = narrow<DTYPE>(x); py[0].v[i] = narrow<DTYPE>(y);
+                box_muller(z2, z3, x, y);
+                px[1].v[i] = narrow<DTYPE>(x); py[1].v[i] = narrow<DTYPE>(y);
+                box_muller(z4, z5, x, y);
+                px[2].v[i] = narrow<DTYPE>(x); py[2].v[i] = narrow<DTYPE>(y);
+            }
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, px[p]);
+                row += rowstep;
+                store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, py[p]);
+                row += rowstep;
+            }
         }
         for (; k < kend; ++k) {
-            double xv, yv;
-            auto z0 = e.step_rot();
-            auto z1 = e.step_rot();
-            box_muller(z0, z1, xv, yv);
-            emit_val<DTYPE, NT>(row, lane, xv); row = advance_row<DTYPE>(row, S);
-            emit_val<DTYPE, NT>(row, lane, yv); row = advance_row<DTYPE>(row, S);
+            Pack<T, SPL> px, py;
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                auto z0 = e[i].step_rot();
+                auto z1 = e[i].step_rot();
+                double x, y;
+                box_muller(z0, z1, x, y);
+                px.v[i] = narrow<DTYPE>(x);
+                py.v[i] = narrow<DTYPE>(y);
+            }
+            store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, px);
+            row += rowstep;
+            store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, py);
+            row += rowstep;
         }
         // Ragged tail (at most one pair): X and Y only where they exist.
-        const uint64_t tend = min(u1, units);
+        const uint64_t tend = min(u1, units[0]);
         for (; k < tend; ++k) {
-            double xv, yv;
-            auto z0 = e.step_rot();
-            auto z1 = e.step_rot();
-            box_muller(z0, z1, xv, yv);
-            if (2 * k < cnt) emit_val<DTYPE, NT>(row, lane, xv);
-            row = advance_row<DTYPE>(row, S);
-            if (2 * k + 1 < cnt) emit_val<DTYPE, NT>(row, lane, yv);
-            row = advance_row<DTYPE>(row, S);
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                if (k < units[i]) {
+                    auto z0 = e[i].step_rot();
+                    auto z1 = e[i].step_rot();
+                    double x, y;
+                    box_muller(z0, z1, x, y);
+                    if (2 * k < cnt[i]) store_1<T, NT>(row_rsrc(row, nrec), voff + i * ESZ, narrow<DTYPE>(x));
+                    if (2 * k + 1 < cnt[i])
+                        store_1<T, NT>(row_rsrc(row + rowstep, nrec), voff + i * ESZ, narrow<DTYPE>(y));
+                }
+            }
+            row += 2 * rowstep;
         }
     } else {
         for (; k + 3 <= kend; k += 3) {
-            auto z0 = e.template step<0>();
-            emit1<DIST, DTYPE, NT>(row, lane, z0, inv_rate); row = advance_row<DTYPE>(row, S);
-            auto z1 = e.template step<1>();
-            emit1<DIST, DTYPE, NT>(row, lane, z1, inv_rate); row = advance_row<DTYPE>(row, S);
-            auto z2 = e.template step<2>();
-            emit1<DIST, DTYPE, NT>(row, lane, z2, inv_rate); row = advance_row<DTYPE>(row, S);
+            Pack<T, SPL> p0, p1, p2;
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                p0.v[i] = value1<DIST, DTYPE>(e[i].template step<0>(), inv_rate);
+                p1.v[i] = value1<DIST, DTYPE>(e[i].template step<1>(), inv_rate);
+                p2.v[i] = value1<DIST, DTYPE>(e[i].template step<2>(), inv_rate);
+            }
+            store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, p0);
+            row += rowstep;
+            store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, p1);
+            row += rowstep;
+            store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, p2);
+            row += rowstep;
         }
         for (; k < kend; ++k) {
-            auto z = e.step_rot();
-            emit1<DIST, DTYPE, NT>(row, lane, z, inv_rate); row = advance_row<DTYPE>(row, S);
+            Pack<T, SPL> p;
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) p.v[i] = value1<DIST, DTYPE>(e[i].step_rot(), inv_rate);
+            store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, p);
+            row += rowstep;
         }
-        const uint64_t tend = min(u1, units);
+        const uint64_t tend = min(u1, units[0]);
         for (; k < tend; ++k) {
-            auto z = e.step_rot();
-            emit1<DIST, DTYPE, NT>(row, lane, z, inv_rate); row = advance_row<DTYPE>(row, S);
+#pragma unroll
+            for (int i = 0; i < SPL; ++i)
+                if (k < units[i])
+                    store_1<T, NT>(row_rsrc(row, nrec), voff + i * ESZ,
+                                   value1<DIST, DTYPE>(e[i].step_rot(), inv_rate));
+            row += rowstep;
         }
     }
 
@@ -314,9 +425,14 @@ __global__ void __launch_bounds__(1024) gen_kernel(GenLaunch L) {
     // finalize_kernel advances it after this launch (other chunks of the same
     // stream may not have read it yet).
     if (L.n_chunks == 1) {
-        e.save(x);
 #pragma unroll
-        for (int i = 0; i < 6; ++i) rec[i] = x[i];
+        for (int i = 0; i < SPL; ++i) {
+            uint32_t x[6];
+            e[i].save(x);
+            uint32_t* rec = L.streams + static_cast<uint64_t>(s0 + i) * 18;
+#pragma unroll
+            for (int w = 0; w < 6; ++w) rec[w] = x[w];
+        }
     }
 }
 
@@ -423,22 +539,40 @@ hipError_t launch_advance(uint32_t* streams, uint64_t n, uint64_t steps, hipStre
     return hipGetLastError();
 }
 
-// Automatic launch shape: enough waves to cover the chip several times over
-// (256 CUs x 4 SIMDs), chunks of at least 96 units, at most 65535 chunks.
+// Automatic launch shape, from measurements on MI355X at 2^30 draws over
+// 262,144 streams (interleaved medians):
+//   f64 uniforms   2 streams/lane (16-byte stores), ~2 waves per SIMD, each
+//                  stream whole in one work-item, 256 threads, XCD remap
+//   f32/u32        4 streams/lane, ~4 waves per SIMD, 512 threads, no remap
+//   normal, exp.   VALU-bound: 1 stream/lane, ~16 waves per SIMD
+// Non-temporal stores throughout.  Chunks hold at least 96 units; at most
+// 65535 chunks.  A narrower store is used when n_streams or the output
+// alignment does not allow the wide one.
 void plan_generate(GenLaunch& L) {
-    if (!L.arith) L.arith = kArithInt;
-    if (!L.block) L.block = 256;
+    const int esz = L.dtype == kF64 ? 8 : 4;
+    const bool plain = L.dist == kUniform || L.dist == kRaw;
+    const bool cfg_given = L.block || L.chunk || L.spl || L.arith;
+    if (!L.arith) L.arith = kArithF64;
+    if (!L.spl) L.spl = plain ? 16 / esz : 1;
+    if (!L.block) L.block = (plain && esz == 4) ? 512 : 256;
+    if (!cfg_given) {
+        L.nontemporal = 1;
+        L.xcd = !(plain && esz == 4);
+    }
+    // at most 16 bytes per store; narrower when the shape does not allow it
+    while (L.spl * esz > 16) L.spl /= 2;
+    while (L.spl > 1 && (L.S % L.spl || reinterpret_cast<uintptr_t>(L.out) % (L.spl * esz))) L.spl /= 2;
     const uint64_t cnt_max = L.q + (L.r ? 1 : 0);
     const uint64_t units_max = L.dist == kNormal ? (cnt_max + 1) / 2 : cnt_max;
-    const uint64_t n_sblk = (static_cast<uint64_t>(L.S) + 63) / 64;
+    const uint64_t ws = 64ull * L.spl;
+    const uint64_t n_sblk = (static_cast<uint64_t>(L.S) + ws - 1) / ws;
     if (!L.chunk) {
-        const uint64_t target_waves = 16384;
+        const uint64_t target_waves = !plain ? 16384 : (esz == 8 ? 2048 : 4096);
         uint64_t w = (target_waves + n_sblk - 1) / n_sblk;
         uint64_t w_cap = (units_max + 95) / 96;
         if (w > w_cap) w = w_cap;
         if (w < 1) w = 1;
         uint64_t c = (units_max + w - 1) / w;
-        c = (c + 2) / 3 * 3;
         L.chunk = static_cast<uint32_t>(c > 0xffffffffull ? 0xffffffffull : (c ? c : 1));
     }
     uint64_t nch = units_max ? (units_max + L.chunk - 1) / L.chunk : 0;
@@ -448,24 +582,42 @@ void plan_generate(GenLaunch& L) {
         nch = (units_max + c - 1) / c;
     }
     L.n_chunks = static_cast<uint32_t>(nch);
+    const uint64_t wpb = static_cast<uint64_t>(L.block) / 64;
+    const uint64_t gx = (n_sblk + wpb - 1) / wpb;
+    if (L.xcd && (gx * nch) % 8) L.xcd = 0;  // the remap needs a multiple of 8 blocks
 }
 
-template <int DIST, int DTYPE, int ARITH, bool NT>
+template <int DIST, int DTYPE, int ARITH, int SPL, bool NT>
 static hipError_t launch_t(const GenLaunch& L, hipStream_t s) {
     const unsigned wpb = static_cast<unsigned>(L.block) / 64;
-    const uint64_t n_sblk = (static_cast<uint64_t>(L.S) + 63) / 64;
+    const uint64_t ws = 64ull * SPL;
+    const uint64_t n_sblk = (static_cast<uint64_t>(L.S) + ws - 1) / ws;
     dim3 grid(static_cast<unsigned>((n_sblk + wpb - 1) / wpb), L.n_chunks);
-    hipLaunchKernelGGL((gen_kernel<DIST, DTYPE, ARITH, NT>), grid, dim3(L.block), 0, s, L);
+    hipLaunchKernelGGL((gen_kernel<DIST, DTYPE, ARITH, SPL, NT>), grid, dim3(L.block), 0, s, L);
     return hipGetLastError();
+}
+
+template <int DIST, int DTYPE, int ARITH, int SPL>
+static hipError_t launch_nt(const GenLaunch& L, hipStream_t s) {
+    return L.nontemporal ? launch_t<DIST, DTYPE, ARITH, SPL, true>(L, s)
+                         : launch_t<DIST, DTYPE, ARITH, SPL, false>(L, s);
+}
+
+template <int DIST, int DTYPE, int ARITH>
+static hipError_t launch_spl(const GenLaunch& L, hipStream_t s) {
+    if constexpr (DTYPE == kF64) {
+        if (L.spl == 2) return launch_nt<DIST, DTYPE, ARITH, 2>(L, s);
+    } else {
+        if (L.spl == 4) return launch_nt<DIST, DTYPE, ARITH, 4>(L, s);
+        if (L.spl == 2) return launch_nt<DIST, DTYPE, ARITH, 2>(L, s);
+    }
+    return launch_nt<DIST, DTYPE, ARITH, 1>(L, s);
 }
 
 template <int DIST, int DTYPE>
 static hipError_t launch_dd(const GenLaunch& L, hipStream_t s) {
-    if (L.arith == kArithF64)
-        return L.nontemporal ? launch_t<DIST, DTYPE, kArithF64, true>(L, s)
-                             : launch_t<DIST, DTYPE, kArithF64, false>(L, s);
-    return L.nontemporal ? launch_t<DIST, DTYPE, kArithInt, true>(L, s)
-                         : launch_t<DIST, DTYPE, kArithInt, false>(L, s);
+    if (L.arith == kArithF64) return launch_spl<DIST, DTYPE, kArithF64>(L, s);
+    return launch_spl<DIST, DTYPE, kArithInt>(L, s);
 }
 
 static hipError_t launch_gen_only(const GenLaunch& L, hipStream_t s) {

@@ -124,7 +124,8 @@ def test_generate_argument_validation_no_side_effects():
 
 def test_launch_cfg_validation():
     L = P.lib()
-    for cfg in [(100, 0, 0, 0), (256, 0, 2, 0), (256, 0, 0, 3)]:
+    for cfg in [(100, 0, 0, 0, 0, 0), (256, 0, 2, 0, 0, 0), (256, 0, 0, 3, 0, 0),
+                (256, 0, 0, 0, 3, 0), (256, 0, 0, 0, 8, 0), (256, 0, 0, 0, 0, 2)]:
         c = P.mrg_launch_cfg(*cfg)
         st = L.mrg_generate_ex(1, ctypes.c_void_p(256), 4, 10, 0, 0, 1.0, ctypes.c_void_p(256),
                                ctypes.byref(c), None)

@@ -102,7 +102,10 @@ CFGS = [None,
         dict(block=64, chunk=1, arith=1), dict(block=64, chunk=1, arith=2),
         dict(block=128, chunk=2, arith=1), dict(block=1024, chunk=5, arith=2, nontemporal=1),
         dict(block=256, chunk=64, arith=1, nontemporal=1), dict(block=512, chunk=7, arith=2),
-        dict(block=256, chunk=100000, arith=1)]
+        dict(block=256, chunk=100000, arith=1),
+        dict(streams_per_lane=1, arith=2), dict(streams_per_lane=2, arith=1, chunk=9),
+        dict(streams_per_lane=2, arith=2, xcd_remap=1, nontemporal=1),
+        dict(streams_per_lane=2, arith=2, xcd_remap=1, block=64, chunk=3)]
 
 
 @pytest.mark.parametrize("cfg", CFGS, ids=lambda c: str(c))
@@ -112,13 +115,16 @@ def test_schedule_invariance_uniform(cfg):
     run_case(rec, 300 * 37 + 123, P.MRG_UNIFORM, P.MRG_F64, cfg=cfg)
 
 
-@pytest.mark.parametrize("cfg", [dict(arith=1, chunk=4), dict(arith=2, chunk=3), dict(arith=2, chunk=0)],
+@pytest.mark.parametrize("cfg", [dict(arith=1, chunk=4), dict(arith=2, chunk=3), dict(arith=2, chunk=0),
+                                 dict(arith=1, chunk=5, streams_per_lane=4, xcd_remap=1),
+                                 dict(arith=2, chunk=2, streams_per_lane=2, nontemporal=1)],
                          ids=str)
 @pytest.mark.parametrize("dist,dtype", [(P.MRG_UNIFORM, P.MRG_F32), (P.MRG_RAW, P.MRG_U32),
                                         (P.MRG_NORMAL, P.MRG_F64), (P.MRG_NORMAL, P.MRG_F32),
                                         (P.MRG_EXPONENTIAL, P.MRG_F64),
                                         (P.MRG_EXPONENTIAL, P.MRG_F32)])
-@pytest.mark.parametrize("S,n", [(77, 77 * 20), (77, 77 * 21 + 5), (130, 130 * 9 + 129), (1, 1001)])
+@pytest.mark.parametrize("S,n", [(77, 77 * 20), (77, 77 * 21 + 5), (130, 130 * 9 + 129), (1, 1001),
+                                 (256, 256 * 13 + 255), (260, 260 * 7 + 1)])
 def test_distributions(cfg, dist, dtype, S, n):
     rec = O.create_streams(GEN, workloads.random_seed(S + n), S)
     run_case(rec, n, dist, dtype, 1.0, cfg)
@@ -162,6 +168,25 @@ def test_extreme_states():
     for cfg in (dict(arith=1), dict(arith=2)):
         run_case(rec, 5 * 40, P.MRG_RAW, P.MRG_U32, cfg=cfg)
         run_case(rec, 5 * 40, P.MRG_UNIFORM, P.MRG_F32, cfg=cfg)
+
+
+@pytest.mark.parametrize("spl", [1, 2, 4])
+def test_misaligned_output_and_odd_stream_counts(spl):
+    """Outputs offset by one element and stream counts not divisible by the
+    requested streams per lane fall back to narrower stores, same bits."""
+    for S in (130, 131, 388):
+        rec = O.create_streams(GEN, workloads.random_seed(S), S)
+        n = S * 10 + 3
+        d = dev_streams(rec)
+        buf = torch.zeros(n + 1, dtype=torch.float32, device="cuda")
+        view = buf[1:]
+        P.mrg_generate(d, n, P.MRG_UNIFORM, P.MRG_F32, out=view, cfg=dict(streams_per_lane=spl))
+        torch.cuda.synchronize()
+        work = rec.copy()
+        want = O.generate(GEN, work, n, O.UNIFORM, O.F32)
+        assert np.array_equal(view.cpu().numpy(), want)
+        assert buf[0].item() == 0.0
+        np.testing.assert_array_equal(P.as_u32(d), work)
 
 
 def test_many_chunks_one_stream():
