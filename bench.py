@@ -6,6 +6,7 @@ stream, element k*S + s = draw k of stream s) + the state write-back.
 Inputs and outputs stay in HBM.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--copy-probe]
+    python bench.py --pmc-summary FETCH_CSV WRITE_CSV
 """
 import argparse
 import json
@@ -22,6 +23,9 @@ S_STREAMS = 262144
 PER_STREAM = 4096
 N = S_STREAMS * PER_STREAM
 HBM_PEAK_GBPS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2201_06604_amd", "csrc", "mrg_kernels.hip")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "gen_kernel_uniform_f64_262144x4096_traffic.json")
+COPY_PROBE_BYTES = 1 << 30
 
 
 def parse():
@@ -33,9 +37,64 @@ def parse():
     ap.add_argument("--no-variants", action="store_true", help="skip f32/normal/exponential timings")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--traffic", type=str, default=None,
-                    help="JSON file with measured HBM traffic per launch (bytes)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of a "
+                         "--copy-probe run into the traffic summary under profiles/, then exit")
     return ap.parse_args()
+
+
+def kernel_sha():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def pmc_summary(fetch_csv, write_csv):
+    """HBM bytes per launch of the fp64-uniform generate kernel from the
+    FETCH_SIZE and WRITE_SIZE counters (KiB per dispatch), each scaled by what
+    the same counter reads for the 1 GiB copy of --copy-probe."""
+    import csv
+
+    def per_kernel(path, counter):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+
+    def pick(d, pred):
+        ks = [k for k in d if pred(k)]
+        assert len(ks) == 1, ks
+        return d[ks[0]], ks[0]
+
+    is_gen = lambda k: "gen_kernel<0, 0," in k
+    is_copy = lambda k: "copyBuffer" in k
+    g_f, name = pick(fetch, is_gen)
+    g_w, _ = pick(write, is_gen)
+    c_f, _ = pick(fetch, is_copy)
+    c_w, _ = pick(write, is_copy)
+    kib = COPY_PROBE_BYTES / 1024.0
+    f_fac, w_fac = kib / c_f, kib / c_w
+    out = {"kernel": name, "workload": "262144 streams x 4096 fp64 uniforms",
+           "fetch_kib": g_f, "write_kib": g_w, "copy_fetch_kib": c_f, "copy_write_kib": c_w,
+           "fetch_factor": f_fac, "write_factor": w_fac,
+           "bytes_per_launch": (g_f * f_fac + g_w * w_fac) * 1024.0,
+           "source_sha256": kernel_sha()}
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+def measured_traffic():
+    """Traffic per launch, only while the kernel source is the one measured."""
+    if not os.path.exists(TRAFFIC_JSON):
+        return None
+    with open(TRAFFIC_JSON) as f:
+        t = json.load(f)
+    return t["bytes_per_launch"] if t.get("source_sha256") == kernel_sha() else None
 
 
 def cpu_baseline(seed):
@@ -57,6 +116,9 @@ def cpu_baseline(seed):
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
               "(streams shard by block across GPUs with no exchange; see the design notes).",
@@ -102,10 +164,7 @@ def main():
     alg_bytes = N * 8 + S_STREAMS * 48  # output + state read and written
     achieved = alg_bytes / (gen_avg_ms * 1e-3) / 1e9
 
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            traffic = json.load(f).get("bytes_per_launch")
+    traffic = measured_traffic()
 
     res = {
         "metric": "GSamples/s MRG32k3a fp64 uniforms (bit-exact); p99 latency, batched vs plain",
@@ -127,7 +186,8 @@ def main():
                    "out_dtype": "f64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic,
+                     "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                     "traffic_unit": "GB per launch",
                      "kernel": "gen_kernel<uniform,f64>", "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": round(gen_avg_ms, 4)},
     }
@@ -163,7 +223,7 @@ def main():
         res["variants"] = var
 
     if args.copy_probe:
-        a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        a = torch.empty(COPY_PROBE_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
