@@ -185,6 +185,81 @@ mrg_status mrg_streams_export(mrg_generator gen, const mrg_stream* dev, size_t n
 mrg_status mrg_streams_import(mrg_generator gen, const void* host_buf, size_t len, mrg_stream* dev,
                               size_t n, size_t* n_out, mrg_creator* creator, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Batching: many generation requests of uneven lengths, each on its own
+ * streams, in one persistent launch (graph-capturable).  Every request gives
+ * exactly the numbers and final states that mrg_generate would give for it.
+ * The paper launches once per call with a fixed work-item grid (Section 2.2);
+ * batching is this library's own extension of that call.
+ * ------------------------------------------------------------------------ */
+
+/* One request: as the arguments of mrg_generate.  `streams` (device, room for
+ * n_streams records) and `out` (device, n elements) belong to the caller;
+ * different requests of one plan must not share stream records or output
+ * bytes. */
+typedef struct {
+    mrg_stream* streams;
+    uint32_t n_streams;
+    uint64_t n;
+    mrg_dist dist;
+    mrg_dtype dtype;
+    double param;
+    void* out;
+} mrg_request;
+
+/* Batch launch shape (0 = automatic for every field).  Results never depend
+ * on it.
+ *   tile_units      most draws (normal: pairs) one wave makes in one tile
+ *   waves_per_simd  resident waves per SIMD of the persistent grid (1..16)
+ *   wide_stores     0 = automatic (16-byte stores where a request allows),
+ *                   1 = force one stream per lane                        */
+typedef struct {
+    uint32_t tile_units;
+    uint32_t waves_per_simd;
+    uint32_t wide_stores;
+} mrg_batch_cfg;
+
+typedef struct mrg_batch_plan mrg_batch_plan;  /* opaque, owned by the library */
+
+/* Host-only: validate the requests (as mrg_generate does, plus disjoint
+ * stream ranges), cut them into tiles (request, block of 64 x SPL streams,
+ * <= tile_units draw units) sorted by estimated cost, longest first. */
+mrg_status mrg_batch_plan_create(mrg_generator gen, const mrg_request* reqs, size_t n_req,
+                                 const mrg_batch_cfg* cfg, mrg_batch_plan** plan);
+void       mrg_batch_plan_destroy(mrg_batch_plan* plan);
+
+/* Device workspace the caller provides for a plan (256-byte aligned), and
+ * the plan's tile count. */
+mrg_status mrg_batch_workspace_size(const mrg_batch_plan* plan, size_t* bytes);
+mrg_status mrg_batch_tile_count(const mrg_batch_plan* plan, size_t* tiles);
+
+/* Copy the plan's static tables into `dev_workspace` (once per workspace and
+ * plan; returns after the copy completed). */
+mrg_status mrg_batch_upload(const mrg_batch_plan* plan, void* dev_workspace, hipStream_t stream);
+
+/* Enqueue the batch on `stream`: a counter-reset kernel, the persistent
+ * kernel and (when a request is split over chunks) a state-advance kernel.
+ * No host synchronisation, no allocation, no memset: may be captured in a
+ * hipGraph and replayed; one workspace serves one launch at a time. */
+mrg_status mrg_batch_launch(const mrg_batch_plan* plan, void* dev_workspace, hipStream_t stream);
+
+/* After a launch has completed: host_ticks[0] = device real-time clock
+ * (100 MHz) when the first tile was taken, host_ticks[1 + r] = when request r
+ * finished storing its output (0 if it did not).  n_req + 1 entries.  Copies
+ * and synchronises `stream`. */
+mrg_status mrg_batch_request_times(const mrg_batch_plan* plan, const void* dev_workspace,
+                                   uint64_t* host_ticks, hipStream_t stream);
+
+/* Autotuner: time candidate shapes (tile_units x waves_per_simd) of the plan
+ * on the GPU with its own requests, in `dev_workspace` (capacity
+ * `workspace_bytes`; shapes whose workspace would not fit are skipped), keep
+ * the fastest in the plan (re-cut and uploaded again) and report it in
+ * `best` / `best_ms` (optional).  Every request's stream records are saved to
+ * host memory first and restored at the end, so the streams are left as they
+ * were; the outputs are overwritten.  Synchronises `stream`. */
+mrg_status mrg_batch_autotune(mrg_batch_plan* plan, void* dev_workspace, size_t workspace_bytes,
+                              hipStream_t stream, mrg_batch_cfg* best, double* best_ms);
+
 #ifdef __cplusplus
 }
 #endif

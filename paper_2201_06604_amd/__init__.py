@@ -53,6 +53,17 @@ def launch_cfg(cfg):
     return mrg_launch_cfg(*[int(cfg.get(k, 0)) for k in CFG_KEYS])
 
 
+class mrg_request(ctypes.Structure):
+    _fields_ = [("streams", ctypes.c_void_p), ("n_streams", ctypes.c_uint32), ("n", ctypes.c_uint64),
+                ("dist", ctypes.c_int), ("dtype", ctypes.c_int), ("param", ctypes.c_double),
+                ("out", ctypes.c_void_p)]
+
+
+class mrg_batch_cfg(ctypes.Structure):
+    _fields_ = [("tile_units", ctypes.c_uint32), ("waves_per_simd", ctypes.c_uint32),
+                ("wide_stores", ctypes.c_uint32)]
+
+
 _lib = None
 
 
@@ -84,6 +95,16 @@ def lib():
             "mrg_streams_export_size": (i32, [sz, i32, ctypes.POINTER(sz)]),
             "mrg_streams_export": (i32, [i32, vp, sz, crp, vp, sz, ctypes.POINTER(sz), vp]),
             "mrg_streams_import": (i32, [i32, vp, sz, vp, sz, ctypes.POINTER(sz), crp, vp]),
+            "mrg_batch_plan_create": (i32, [i32, ctypes.POINTER(mrg_request), sz,
+                                            ctypes.POINTER(mrg_batch_cfg), ctypes.POINTER(vp)]),
+            "mrg_batch_plan_destroy": (None, [vp]),
+            "mrg_batch_workspace_size": (i32, [vp, ctypes.POINTER(sz)]),
+            "mrg_batch_tile_count": (i32, [vp, ctypes.POINTER(sz)]),
+            "mrg_batch_upload": (i32, [vp, vp, vp]),
+            "mrg_batch_launch": (i32, [vp, vp, vp]),
+            "mrg_batch_request_times": (i32, [vp, vp, ctypes.POINTER(ctypes.c_uint64), vp]),
+            "mrg_batch_autotune": (i32, [vp, vp, sz, vp, ctypes.POINTER(mrg_batch_cfg),
+                                         ctypes.POINTER(ctypes.c_double)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -96,7 +117,10 @@ def lib():
 EXPORTED = ["mrg_abi_version", "mrg_status_string", "mrg_last_error", "mrg_seed_check",
             "mrg_creator_init", "mrg_streams_create_host", "mrg_streams_create_device",
             "mrg_streams_reset", "mrg_streams_advance", "mrg_generate", "mrg_generate_ex",
-            "mrg_streams_export_size", "mrg_streams_export", "mrg_streams_import"]
+            "mrg_streams_export_size", "mrg_streams_export", "mrg_streams_import",
+            "mrg_batch_plan_create", "mrg_batch_plan_destroy", "mrg_batch_workspace_size",
+            "mrg_batch_tile_count", "mrg_batch_upload", "mrg_batch_launch",
+            "mrg_batch_request_times", "mrg_batch_autotune"]
 
 
 def _check(st):
@@ -247,3 +271,71 @@ def mrg_streams_import(data, out, creator=None, gen=MRG_GEN_MRG32K3A, stream=Non
 def as_u32(t):
     """Device int32 tensor -> host numpy uint32 (bit reinterpretation)."""
     return t.detach().cpu().numpy().view(np.uint32)
+
+
+# ------------------------------------------------------------------ batching
+def make_request(streams, n, dist, dtype, param=1.0, out=None, n_streams=None):
+    """mrg_request for device tensors `streams` ((S,18) int32) and `out`."""
+    S = streams.shape[0] if n_streams is None else n_streams
+    return mrg_request(streams.data_ptr() if streams is not None else None, S, n, dist, dtype, param,
+                       out.data_ptr() if out is not None else None)
+
+
+class BatchPlan:
+    """Owns an mrg_batch_plan; the device workspace is a torch uint8 tensor."""
+
+    def __init__(self, requests, cfg=None, gen=MRG_GEN_MRG32K3A):
+        arr = (mrg_request * max(len(requests), 1))(*requests)
+        c = None if cfg is None else ctypes.byref(mrg_batch_cfg(cfg.get("tile_units", 0),
+                                                                cfg.get("waves_per_simd", 0),
+                                                                cfg.get("wide_stores", 0)))
+        self._p = ctypes.c_void_p()
+        _check(lib().mrg_batch_plan_create(gen, arr, len(requests), c, ctypes.byref(self._p)))
+        self.n_req = len(requests)
+        self.workspace = None
+
+    def __del__(self):
+        if getattr(self, "_p", None) and self._p.value and _lib is not None:
+            _lib.mrg_batch_plan_destroy(self._p)
+            self._p = None
+
+    def workspace_size(self):
+        b = ctypes.c_size_t()
+        _check(lib().mrg_batch_workspace_size(self._p, ctypes.byref(b)))
+        return b.value
+
+    def tile_count(self):
+        b = ctypes.c_size_t()
+        _check(lib().mrg_batch_tile_count(self._p, ctypes.byref(b)))
+        return b.value
+
+    def alloc_workspace(self, nbytes=None, device="cuda"):
+        import torch
+        nbytes = self.workspace_size() if nbytes is None else nbytes
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws_ptr = self.workspace.data_ptr() + off
+        self._ws_bytes = nbytes
+        return self._ws_ptr
+
+    def upload(self, stream=None):
+        if self.workspace is None:
+            self.alloc_workspace()
+        _check(lib().mrg_batch_upload(self._p, ctypes.c_void_p(self._ws_ptr), _stream(stream)))
+
+    def launch(self, stream=None):
+        _check(lib().mrg_batch_launch(self._p, ctypes.c_void_p(self._ws_ptr), _stream(stream)))
+
+    def request_times(self, stream=None):
+        """Device real-time clock ticks (100 MHz): [start, done_0, ..., done_{n-1}]."""
+        t = (ctypes.c_uint64 * (self.n_req + 1))()
+        _check(lib().mrg_batch_request_times(self._p, ctypes.c_void_p(self._ws_ptr), t, _stream(stream)))
+        return np.array(list(t), dtype=np.uint64)
+
+    def autotune(self, stream=None):
+        best = mrg_batch_cfg()
+        ms = ctypes.c_double()
+        _check(lib().mrg_batch_autotune(self._p, ctypes.c_void_p(self._ws_ptr), self._ws_bytes,
+                                        _stream(stream), ctypes.byref(best), ctypes.byref(ms)))
+        return dict(tile_units=best.tile_units, waves_per_simd=best.waves_per_simd,
+                    wide_stores=best.wide_stores), ms.value

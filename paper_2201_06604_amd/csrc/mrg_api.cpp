@@ -17,11 +17,10 @@
 
 using namespace mrg355;
 
-namespace {
+static thread_local std::string g_err;
 
-thread_local std::string g_err;
-
-mrg_status fail(mrg_status st, const char* fmt, ...) {
+// Record the message of a failing call (thread-local) and return its status.
+mrg_status mrg355_fail(mrg_status st, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -30,6 +29,10 @@ mrg_status fail(mrg_status st, const char* fmt, ...) {
     g_err = buf;
     return st;
 }
+
+namespace {
+
+#define fail mrg355_fail
 
 mrg_status ok() { return MRG_OK; }
 

@@ -1,0 +1,370 @@
+// mrg_batch.cpp -- host side of batched generation: plans (tiles, workspace
+// layout), upload, launch, completion times and the autotuner.
+//
+// A request is the argument list of one mrg_generate call.  A plan cuts every
+// request into tiles -- (request, block of 64*SPL streams, chunk of at most
+// tile_units draw units) -- and orders them by estimated cost, longest first,
+// so that the persistent kernel's waves, which take tiles from one atomic
+// counter, finish together.  Each tile runs exactly the code of the plain
+// generate kernel for its piece, so results are identical to per-request
+// launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "mrg355.h"
+#include "mrg_internal.h"
+#include "mrg_math.h"
+
+using namespace mrg355;
+
+mrg_status mrg355_fail(mrg_status st, const char* fmt, ...);  // mrg_api.cpp
+
+struct mrg_batch_plan {
+    mrg_generator gen;
+    std::vector<mrg_request> user;
+    uint32_t tile_units;
+    uint32_t waves_per_simd;
+    uint32_t wide;
+    std::vector<BatchReq> reqs;
+    std::vector<BatchTile> tiles;
+    std::vector<uint32_t> fin_req;
+    std::vector<uint64_t> fin_pre;
+    uint64_t fin_total;
+    size_t off_slots, off_reqs, off_tiles, off_fin_req, off_fin_pre, bytes;
+};
+
+namespace {
+
+constexpr uint32_t kDefaultTileUnits = 4096;
+constexpr uint32_t kDefaultWavesPerSimd = 8;
+constexpr unsigned kBatchBlock = 256;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t esz_of(mrg_dtype dt) { return dt == MRG_F64 ? 8 : 4; }
+
+// Estimated VALU cost of one draw unit per stream (uniform steps ~20 ops;
+// the fp64 logarithm, square root and sincospi dominate the transforms).
+double unit_cost(int dist) {
+    switch (dist) {
+        case kNormal: return 240.0;
+        case kExponential: return 130.0;
+        default: return 20.0;
+    }
+}
+
+mrg_status validate_request(const mrg_request& q, size_t i) {
+    const mrg_dist dist = q.dist;
+    const mrg_dtype dtype = q.dtype;
+    if (dist != MRG_UNIFORM && dist != MRG_NORMAL && dist != MRG_EXPONENTIAL && dist != MRG_RAW)
+        return mrg355_fail(MRG_E_INVALID_ARG, "request %zu: unknown distribution", i);
+    if (dtype != MRG_F64 && dtype != MRG_F32 && dtype != MRG_U32)
+        return mrg355_fail(MRG_E_INVALID_ARG, "request %zu: unknown dtype", i);
+    if ((dist == MRG_RAW) != (dtype == MRG_U32))
+        return mrg355_fail(MRG_E_INVALID_ARG, "request %zu: MRG_RAW pairs with MRG_U32 only", i);
+    if (dist == MRG_EXPONENTIAL && !(std::isfinite(q.param) && q.param > 0.0))
+        return mrg355_fail(MRG_E_INVALID_ARG, "request %zu: exponential rate must be finite and > 0", i);
+    if (q.n == 0) return MRG_OK;
+    if (q.n_streams == 0) return mrg355_fail(MRG_E_INVALID_ARG, "request %zu: no streams", i);
+    if (q.n_streams > (1u << 31)) return mrg355_fail(MRG_E_INVALID_ARG, "request %zu: too many streams", i);
+    if (!q.streams || !q.out) return mrg355_fail(MRG_E_INVALID_ARG, "request %zu: NULL pointer", i);
+    if (reinterpret_cast<uintptr_t>(q.out) % esz_of(dtype))
+        return mrg355_fail(MRG_E_INVALID_ARG, "request %zu: output misaligned", i);
+    if (reinterpret_cast<uintptr_t>(q.streams) % 4)
+        return mrg355_fail(MRG_E_INVALID_ARG, "request %zu: streams misaligned", i);
+    return MRG_OK;
+}
+
+// Byte ranges [lo, hi) must not overlap.
+bool disjoint(std::vector<std::pair<uintptr_t, uintptr_t>> v) {
+    std::sort(v.begin(), v.end());
+    for (size_t i = 1; i < v.size(); ++i)
+        if (v[i].first < v[i - 1].second) return false;
+    return true;
+}
+
+// (Re)cut the plan's requests into tiles for its tile_units / wide setting.
+mrg_status build(mrg_batch_plan& P) {
+    P.reqs.clear();
+    P.tiles.clear();
+    P.fin_req.clear();
+    P.fin_pre.assign(1, 0);
+    std::vector<double> cost;
+    for (size_t i = 0; i < P.user.size(); ++i) {
+        const mrg_request& q = P.user[i];
+        BatchReq R{};
+        GenLaunch& L = R.L;
+        L.streams = reinterpret_cast<uint32_t*>(q.streams);
+        L.out = q.out;
+        L.dist = static_cast<int>(q.dist);
+        L.dtype = static_cast<int>(q.dtype);
+        L.arith = kArithF64;
+        L.nontemporal = 1;
+        L.block = kBatchBlock;
+        L.param = q.dist == MRG_EXPONENTIAL ? 1.0 / q.param : 1.0;
+        const int esz = static_cast<int>(esz_of(q.dtype));
+        const bool plain = q.dist == MRG_UNIFORM || q.dist == MRG_RAW;
+        int spl = (plain && P.wide != 1) ? 16 / esz : 1;
+        while (spl > 1 && (q.n_streams % spl || reinterpret_cast<uintptr_t>(q.out) % (spl * esz))) spl /= 2;
+        if (esz == 4 && spl == 2) spl = 1;  // tiles of 4-byte outputs use 1 or 4 streams per lane
+        L.spl = spl;
+        R.kind = static_cast<uint32_t>(batch_kind(L.dist, L.dtype, spl));
+        if (q.n == 0) {
+            P.reqs.push_back(R);
+            continue;
+        }
+        L.S = q.n_streams;
+        L.q = q.n / q.n_streams;
+        L.r = static_cast<uint32_t>(q.n % q.n_streams);
+        const uint64_t cnt_max = L.q + (L.r ? 1 : 0);
+        const uint64_t units = L.dist == kNormal ? (cnt_max + 1) / 2 : cnt_max;
+        const uint64_t chunk = std::min<uint64_t>(units, P.tile_units);
+        const uint64_t n_chunks = (units + chunk - 1) / chunk;
+        L.chunk = static_cast<uint32_t>(chunk);
+        L.n_chunks = static_cast<uint32_t>(n_chunks);
+        const uint64_t n_sblk = (static_cast<uint64_t>(L.S) + 64 * spl - 1) / (64 * spl);
+        const uint64_t nt = n_sblk * n_chunks;
+        if (P.tiles.size() + nt > 0xffffffffull) return mrg355_fail(MRG_E_INVALID_ARG, "too many tiles");
+        R.n_tiles = static_cast<uint32_t>(nt);
+        for (uint64_t sb = 0; sb < n_sblk; ++sb)
+            for (uint64_t j = 0; j < n_chunks; ++j) {
+                const uint64_t u = std::min<uint64_t>(chunk, units - j * chunk);
+                P.tiles.push_back(BatchTile{static_cast<uint32_t>(i), static_cast<uint32_t>(sb),
+                                            static_cast<uint32_t>(j), 0});
+                cost.push_back(static_cast<double>(u) * unit_cost(L.dist) * spl);
+            }
+        if (n_chunks > 1) {
+            P.fin_req.push_back(static_cast<uint32_t>(i));
+            P.fin_pre.push_back(P.fin_pre.back() + L.S);
+        }
+        P.reqs.push_back(R);
+    }
+    // longest first; ties keep request order
+    std::vector<uint32_t> order(P.tiles.size());
+    for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
+    std::vector<BatchTile> sorted(P.tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) sorted[i] = P.tiles[order[i]];
+    P.tiles.swap(sorted);
+    P.fin_total = P.fin_pre.back();
+    // workspace layout
+    const size_t n_req = P.reqs.size();
+    P.off_slots = 256;
+    P.off_reqs = align_up(P.off_slots + n_req * sizeof(BatchSlot), 256);
+    P.off_tiles = align_up(P.off_reqs + n_req * sizeof(BatchReq), 256);
+    P.off_fin_req = align_up(P.off_tiles + P.tiles.size() * sizeof(BatchTile), 256);
+    P.off_fin_pre = align_up(P.off_fin_req + P.fin_req.size() * sizeof(uint32_t), 256);
+    P.bytes = align_up(P.off_fin_pre + P.fin_pre.size() * sizeof(uint64_t), 256);
+    return MRG_OK;
+}
+
+BatchLaunch launch_args(const mrg_batch_plan& P, void* ws) {
+    char* base = static_cast<char*>(ws);
+    BatchLaunch B{};
+    B.head = reinterpret_cast<BatchHeader*>(base);
+    B.slots = reinterpret_cast<BatchSlot*>(base + P.off_slots);
+    B.reqs = reinterpret_cast<const BatchReq*>(base + P.off_reqs);
+    B.tiles = reinterpret_cast<const BatchTile*>(base + P.off_tiles);
+    B.fin_req = reinterpret_cast<const uint32_t*>(base + P.off_fin_req);
+    B.fin_pre = reinterpret_cast<const uint64_t*>(base + P.off_fin_pre);
+    B.n_req = static_cast<uint32_t>(P.reqs.size());
+    B.n_tiles = static_cast<uint32_t>(P.tiles.size());
+    B.n_fin = static_cast<uint32_t>(P.fin_req.size());
+    B.fin_total = P.fin_total;
+    return B;
+}
+
+mrg_status upload(const mrg_batch_plan& P, void* ws, hipStream_t stream) {
+    std::vector<char> host(P.bytes - P.off_reqs, 0);
+    auto put = [&](size_t off, const void* src, size_t n) {
+        if (n) std::memcpy(host.data() + (off - P.off_reqs), src, n);
+    };
+    put(P.off_reqs, P.reqs.data(), P.reqs.size() * sizeof(BatchReq));
+    put(P.off_tiles, P.tiles.data(), P.tiles.size() * sizeof(BatchTile));
+    put(P.off_fin_req, P.fin_req.data(), P.fin_req.size() * sizeof(uint32_t));
+    put(P.off_fin_pre, P.fin_pre.data(), P.fin_pre.size() * sizeof(uint64_t));
+    hipError_t e = hipMemcpyAsync(static_cast<char*>(ws) + P.off_reqs, host.data(), host.size(),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return mrg355_fail(MRG_E_HIP, "batch upload: %s", hipGetErrorString(e));
+    return MRG_OK;
+}
+
+mrg_status launch(const mrg_batch_plan& P, void* ws, hipStream_t stream) {
+    if (P.tiles.empty() && P.reqs.empty()) return MRG_OK;
+    const BatchLaunch B = launch_args(P, ws);
+    const uint64_t waves = static_cast<uint64_t>(device_cu_count()) * 4 * P.waves_per_simd;
+    const uint64_t need = (P.tiles.size() + kBatchBlock / 64 - 1) / (kBatchBlock / 64);
+    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(waves / (kBatchBlock / 64), need));
+    hipError_t e = launch_batch(B, static_cast<unsigned>(grid), kBatchBlock, stream);
+    if (e != hipSuccess) return mrg355_fail(MRG_E_HIP, "batch launch: %s", hipGetErrorString(e));
+    return MRG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mrg_status mrg_batch_plan_create(mrg_generator gen, const mrg_request* reqs, size_t n_req,
+                                 const mrg_batch_cfg* cfg, mrg_batch_plan** plan) {
+    if (gen == MRG_GEN_MRG31K3P) return mrg355_fail(MRG_E_UNSUPPORTED, "generator MRG31k3p is not built");
+    if (gen != MRG_GEN_MRG32K3A) return mrg355_fail(MRG_E_INVALID_ARG, "unknown generator id");
+    if (!plan) return mrg355_fail(MRG_E_INVALID_ARG, "plan is NULL");
+    if (n_req && !reqs) return mrg355_fail(MRG_E_INVALID_ARG, "reqs is NULL");
+    if (n_req > 0xfffffffful) return mrg355_fail(MRG_E_INVALID_ARG, "too many requests");
+    if (cfg && cfg->waves_per_simd > 16) return mrg355_fail(MRG_E_INVALID_ARG, "waves_per_simd above 16");
+    if (cfg && cfg->wide_stores > 1) return mrg355_fail(MRG_E_INVALID_ARG, "wide_stores must be 0 or 1");
+    std::vector<std::pair<uintptr_t, uintptr_t>> sr, orng;
+    for (size_t i = 0; i < n_req; ++i) {
+        if (mrg_status st = validate_request(reqs[i], i)) return st;
+        if (reqs[i].n == 0) continue;
+        uintptr_t s0 = reinterpret_cast<uintptr_t>(reqs[i].streams);
+        uintptr_t o0 = reinterpret_cast<uintptr_t>(reqs[i].out);
+        sr.emplace_back(s0, s0 + static_cast<uintptr_t>(reqs[i].n_streams) * sizeof(mrg_stream));
+        orng.emplace_back(o0, o0 + static_cast<uintptr_t>(reqs[i].n) * esz_of(reqs[i].dtype));
+    }
+    if (!disjoint(sr)) return mrg355_fail(MRG_E_INVALID_ARG, "requests share stream records");
+    if (!disjoint(orng)) return mrg355_fail(MRG_E_INVALID_ARG, "requests share output bytes");
+    mrg_batch_plan* P = new (std::nothrow) mrg_batch_plan();
+    if (!P) return mrg355_fail(MRG_E_NOMEM, "plan allocation failed");
+    P->gen = gen;
+    P->user.assign(reqs, reqs + n_req);
+    P->tile_units = (cfg && cfg->tile_units) ? cfg->tile_units : kDefaultTileUnits;
+    P->waves_per_simd = (cfg && cfg->waves_per_simd) ? cfg->waves_per_simd : kDefaultWavesPerSimd;
+    P->wide = cfg ? cfg->wide_stores : 0;
+    mrg_status st = build(*P);
+    if (st) {
+        delete P;
+        return st;
+    }
+    *plan = P;
+    return MRG_OK;
+}
+
+void mrg_batch_plan_destroy(mrg_batch_plan* plan) { delete plan; }
+
+mrg_status mrg_batch_workspace_size(const mrg_batch_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return mrg355_fail(MRG_E_INVALID_ARG, "NULL plan or bytes");
+    *bytes = plan->bytes;
+    return MRG_OK;
+}
+
+mrg_status mrg_batch_tile_count(const mrg_batch_plan* plan, size_t* tiles) {
+    if (!plan || !tiles) return mrg355_fail(MRG_E_INVALID_ARG, "NULL plan or tiles");
+    *tiles = plan->tiles.size();
+    return MRG_OK;
+}
+
+mrg_status mrg_batch_upload(const mrg_batch_plan* plan, void* dev_workspace, hipStream_t stream) {
+    if (!plan || !dev_workspace) return mrg355_fail(MRG_E_INVALID_ARG, "NULL plan or workspace");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
+        return mrg355_fail(MRG_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    return upload(*plan, dev_workspace, stream);
+}
+
+mrg_status mrg_batch_launch(const mrg_batch_plan* plan, void* dev_workspace, hipStream_t stream) {
+    if (!plan || !dev_workspace) return mrg355_fail(MRG_E_INVALID_ARG, "NULL plan or workspace");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
+        return mrg355_fail(MRG_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    return launch(*plan, dev_workspace, stream);
+}
+
+mrg_status mrg_batch_request_times(const mrg_batch_plan* plan, const void* dev_workspace,
+                                   uint64_t* host_ticks, hipStream_t stream) {
+    if (!plan || !dev_workspace || !host_ticks) return mrg355_fail(MRG_E_INVALID_ARG, "NULL argument");
+    const size_t n = plan->reqs.size();
+    std::vector<BatchSlot> slots(n);
+    BatchHeader head{};
+    const char* base = static_cast<const char*>(dev_workspace);
+    hipError_t e = hipMemcpyAsync(&head, base, sizeof(head), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess && n)
+        e = hipMemcpyAsync(slots.data(), base + plan->off_slots, n * sizeof(BatchSlot), hipMemcpyDeviceToHost,
+                           stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return mrg355_fail(MRG_E_HIP, "request times: %s", hipGetErrorString(e));
+    host_ticks[0] = head.t_start;
+    for (size_t i = 0; i < n; ++i) host_ticks[1 + i] = slots[i].done ? slots[i].t_done : 0;
+    return MRG_OK;
+}
+
+mrg_status mrg_batch_autotune(mrg_batch_plan* plan, void* dev_workspace, size_t workspace_bytes,
+                              hipStream_t stream, mrg_batch_cfg* best, double* best_ms) {
+    if (!plan || !dev_workspace) return mrg355_fail(MRG_E_INVALID_ARG, "NULL plan or workspace");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
+        return mrg355_fail(MRG_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    // save every request's stream records
+    std::vector<std::vector<char>> saved(plan->user.size());
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < plan->user.size() && e == hipSuccess; ++i) {
+        const mrg_request& q = plan->user[i];
+        if (!q.n) continue;
+        saved[i].resize(static_cast<size_t>(q.n_streams) * sizeof(mrg_stream));
+        e = hipMemcpyAsync(saved[i].data(), q.streams, saved[i].size(), hipMemcpyDeviceToHost, stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return mrg355_fail(MRG_E_HIP, "autotune save: %s", hipGetErrorString(e));
+
+    const uint32_t orig_tu = plan->tile_units, orig_w = plan->waves_per_simd;
+    const uint32_t tus[] = {1024, 2048, 4096, 8192, 16384};
+    const uint32_t wps[] = {4, 8};
+    double best_t = 1e30;
+    uint32_t best_tu = orig_tu, best_w = orig_w;
+    hipEvent_t a = nullptr, b = nullptr;
+    e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    mrg_status st = MRG_OK;
+    for (uint32_t tu : tus) {
+        if (st || e != hipSuccess) break;
+        plan->tile_units = tu;
+        if ((st = build(*plan))) break;
+        if (plan->bytes > workspace_bytes) continue;  // does not fit the caller's workspace
+        if ((st = upload(*plan, dev_workspace, stream))) break;
+        for (uint32_t w : wps) {
+            plan->waves_per_simd = w;
+            if ((st = launch(*plan, dev_workspace, stream))) break;  // warm-up
+            e = hipEventRecord(a, stream);
+            for (int rep = 0; rep < 2 && !st; ++rep) st = launch(*plan, dev_workspace, stream);
+            if (e == hipSuccess) e = hipEventRecord(b, stream);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (st || e != hipSuccess) break;
+            if (ms / 2 < best_t) {
+                best_t = ms / 2;
+                best_tu = tu;
+                best_w = w;
+            }
+        }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    // restore the streams, keep the best shape
+    for (size_t i = 0; i < plan->user.size() && e == hipSuccess; ++i) {
+        if (saved[i].empty()) continue;
+        e = hipMemcpyAsync(plan->user[i].streams, saved[i].data(), saved[i].size(), hipMemcpyHostToDevice,
+                           stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    plan->tile_units = best_t < 1e30 ? best_tu : orig_tu;
+    plan->waves_per_simd = best_t < 1e30 ? best_w : orig_w;
+    mrg_status st2 = build(*plan);
+    if (st) return st;
+    if (e != hipSuccess) return mrg355_fail(MRG_E_HIP, "autotune: %s", hipGetErrorString(e));
+    if (st2) return st2;
+    if (plan->bytes <= workspace_bytes)
+        if ((st2 = upload(*plan, dev_workspace, stream))) return st2;
+    if (best) {
+        best->tile_units = plan->tile_units;
+        best->waves_per_simd = plan->waves_per_simd;
+        best->wide_stores = plan->wide;
+    }
+    if (best_ms) *best_ms = best_t < 1e30 ? best_t : 0.0;
+    return MRG_OK;
+}
+
+}  // extern "C"

@@ -28,6 +28,50 @@ struct GenLaunch {
 
 // Resolve chunk/n_chunks/block/arith left at 0 to the automatic choice.
 void plan_generate(GenLaunch& L);
+
+// ---------------------------------------------------------------- batching
+// Kinds of tile the persistent kernel can run (dist, dtype, streams per lane).
+enum BatchKind {
+    kBUniF64x1, kBUniF64x2, kBUniF32x1, kBUniF32x4, kBRawU32x1, kBRawU32x4,
+    kBNormF64, kBNormF32, kBExpF64, kBExpF32, kBKinds
+};
+
+struct BatchReq {       // one request, static for a plan
+    GenLaunch L;        // its launch description (chunk = tile units)
+    uint32_t n_tiles;
+    uint32_t kind;
+};
+
+struct BatchTile {      // a wave's unit of work
+    uint32_t req, sblk, chunk, pad;
+};
+
+struct BatchSlot {      // per-request counters, reset by every launch
+    uint32_t remaining; // tiles not finished
+    uint32_t done;      // 1 once every tile has stored its output
+    uint64_t t_done;    // device real-time clock (100 MHz) at completion
+};
+
+struct BatchHeader {    // at workspace offset 0, reset by every launch
+    uint32_t queue;     // next tile to hand out
+    uint32_t started;
+    uint64_t t_start;   // device real-time clock when the first tile was taken
+};
+
+struct BatchLaunch {    // kernel arguments
+    BatchHeader* head;
+    BatchSlot* slots;
+    const BatchReq* reqs;
+    const BatchTile* tiles;
+    const uint32_t* fin_req;  // requests split over chunks (state advanced afterwards)
+    const uint64_t* fin_pre;  // prefix sums of their stream counts
+    uint32_t n_req, n_tiles, n_fin;
+    uint64_t fin_total;
+};
+
+hipError_t launch_batch(const BatchLaunch& B, unsigned grid, unsigned block, hipStream_t s);
+int batch_kind(int dist, int dtype, int spl);
+int device_cu_count();
 hipError_t launch_generate(const GenLaunch& L, hipStream_t s);
 
 hipError_t launch_create(uint32_t* out, uint64_t n, const uint32_t creator[6], hipStream_t s);

@@ -263,31 +263,17 @@ __device__ __forceinline__ void store_1(__amdgpu_buffer_rsrc_t r, uint32_t voff,
 // One wave = 64 lanes x SPL consecutive streams, one chunk of draw indices.
 // Lane l owns streams s0 .. s0+SPL-1, s0 = first + l*SPL, and stores their
 // SPL values of a draw index with one SPL*esz-byte store.
+// One wave's share of one request: stream block `sblk` (64*SPL streams),
+// draw units [by*chunk, (by+1)*chunk).  Wave-uniform arguments.
 template <int DIST, int DTYPE, int ARITH, int SPL, bool NT>
-__global__ void __launch_bounds__(1024) gen_kernel(GenLaunch L) {
+__device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uint32_t by) {
     using Engine = typename std::conditional<ARITH == kArithF64, F64Engine, IntEngine>::type;
     using T = typename ElemOf<DTYPE>::T;
     constexpr uint32_t ESZ = sizeof(T);
     constexpr uint32_t WS = 64 * SPL;                   // streams per wave
     constexpr uint64_t kSpu = DIST == kNormal ? 2 : 1;  // steps per unit
-
-    // Block -> (stream block, chunk).  With xcd remapping, consecutive logical
-    // blocks (neighbouring row segments) land on one XCD, whose L2 then sees
-    // contiguous runs of every row; blocks are dealt to the 8 XCDs in turn.
-    uint32_t bx = blockIdx.x, by = blockIdx.y;
-    if (L.xcd) {
-        const uint32_t total = gridDim.x * gridDim.y;
-        uint32_t lin = blockIdx.x + blockIdx.y * gridDim.x;
-        lin = (lin % 8) * (total / 8) + lin / 8;  // host guarantees total % 8 == 0
-        bx = lin % gridDim.x;
-        by = lin / gridDim.x;
-    }
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t sblk = bx * (blockDim.x >> 6) + wave;
     const uint32_t S = L.S;
-    const uint32_t n_sblk = (S + WS - 1) / WS;
-    if (sblk >= n_sblk) return;
     const uint32_t first = sblk * WS;
     const uint32_t s0 = first + lane * SPL;
     if (s0 >= S) return;  // S % SPL == 0: a lane's streams are all present or all absent
@@ -436,6 +422,25 @@ __global__ void __launch_bounds__(1024) gen_kernel(GenLaunch L) {
     }
 }
 
+template <int DIST, int DTYPE, int ARITH, int SPL, bool NT>
+__global__ void __launch_bounds__(1024) gen_kernel(GenLaunch L) {
+    // Block -> (stream block, chunk).  With xcd remapping, consecutive logical
+    // blocks (neighbouring row segments) land on one XCD, whose L2 then sees
+    // contiguous runs of every row; blocks are dealt to the 8 XCDs in turn.
+    uint32_t bx = blockIdx.x, by = blockIdx.y;
+    if (L.xcd) {
+        const uint32_t total = gridDim.x * gridDim.y;
+        uint32_t lin = blockIdx.x + blockIdx.y * gridDim.x;
+        lin = (lin % 8) * (total / 8) + lin / 8;  // host guarantees total % 8 == 0
+        bx = lin % gridDim.x;
+        by = lin / gridDim.x;
+    }
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t sblk = bx * (blockDim.x >> 6) + wave;
+    if (sblk >= (L.S + 64 * SPL - 1) / (64 * SPL)) return;
+    run_chunk<DIST, DTYPE, ARITH, SPL, NT>(L, sblk, by);
+}
+
 // cur <- A^(steps consumed) cur for every stream, after a chunked launch:
 // cnt_s = q + (s < r) draws; normals consume 2*ceil(cnt_s/2) steps.
 __global__ void __launch_bounds__(256) finalize_kernel(uint32_t* streams, uint32_t S, uint64_t q,
@@ -449,6 +454,107 @@ __global__ void __launch_bounds__(256) finalize_kernel(uint32_t* streams, uint32
 #pragma unroll
     for (int w = 0; w < 6; ++w) x[w] = rec[w];
     for (int b = 0; b < 64; ++b)  // uniform loop: table loads stay scalar
+        if ((steps >> b) & 1) dev_apply(g_tab.step_pow2[0][b], g_tab.step_pow2[1][b], x);
+#pragma unroll
+    for (int w = 0; w < 6; ++w) rec[w] = x[w];
+}
+
+// --------------------------------------------------------------- batching
+// Counters of every request are reset at the start of each launch by a small
+// kernel (no memset node, so the launch can be captured in a graph).
+__global__ void __launch_bounds__(256) batch_init_kernel(BatchLaunch B) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        B.head->queue = 0;
+        B.head->started = 0;
+        B.head->t_start = 0;
+    }
+    if (i < B.n_req) {
+        B.slots[i].remaining = B.reqs[i].n_tiles;
+        B.slots[i].done = 0;
+        B.slots[i].t_done = 0;
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ void batch_tile(const GenLaunch& L, uint32_t sblk, uint32_t chunk) {
+    if constexpr (KIND == kBUniF64x1) run_chunk<kUniform, kF64, kArithF64, 1, true>(L, sblk, chunk);
+    if constexpr (KIND == kBUniF64x2) run_chunk<kUniform, kF64, kArithF64, 2, true>(L, sblk, chunk);
+    if constexpr (KIND == kBUniF32x1) run_chunk<kUniform, kF32, kArithF64, 1, true>(L, sblk, chunk);
+    if constexpr (KIND == kBUniF32x4) run_chunk<kUniform, kF32, kArithF64, 4, true>(L, sblk, chunk);
+    if constexpr (KIND == kBRawU32x1) run_chunk<kRaw, kU32, kArithF64, 1, true>(L, sblk, chunk);
+    if constexpr (KIND == kBRawU32x4) run_chunk<kRaw, kU32, kArithF64, 4, true>(L, sblk, chunk);
+    if constexpr (KIND == kBNormF64) run_chunk<kNormal, kF64, kArithF64, 1, true>(L, sblk, chunk);
+    if constexpr (KIND == kBNormF32) run_chunk<kNormal, kF32, kArithF64, 1, true>(L, sblk, chunk);
+    if constexpr (KIND == kBExpF64) run_chunk<kExponential, kF64, kArithF64, 1, true>(L, sblk, chunk);
+    if constexpr (KIND == kBExpF32) run_chunk<kExponential, kF32, kArithF64, 1, true>(L, sblk, chunk);
+}
+
+// Persistent kernel: every wave takes tiles from one atomic counter until the
+// queue is empty (each wave exits after at most n_tiles + 1 takes).  Tiles
+// were sorted longest first on the host.  After its stores, a wave counts the
+// tile off its request; the wave that finishes a request stamps the device
+// real-time clock into the request's slot.
+//
+// No branch on the lane index surrounds the atomics: every lane executes them
+// with an increment of 1 on lane 0 and 0 elsewhere, and the wave takes lane
+// 0's result with readfirstlane.  The loop's control flow is therefore
+// wave-uniform, and no lane can be left iterating on its own.
+__global__ void __launch_bounds__(256) batch_kernel(BatchLaunch B) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t one = lane == 0 ? 1u : 0u;
+    for (;;) {
+        const uint32_t t = __builtin_amdgcn_readfirstlane(atomicAdd(&B.head->queue, one));
+        if (t >= B.n_tiles) break;
+        if (t == 0) B.head->t_start = __builtin_amdgcn_s_memrealtime();  // same value from every lane
+        const uint32_t req = __builtin_amdgcn_readfirstlane(B.tiles[t].req);
+        const uint32_t sblk = __builtin_amdgcn_readfirstlane(B.tiles[t].sblk);
+        const uint32_t chunk = __builtin_amdgcn_readfirstlane(B.tiles[t].chunk);
+        const uint32_t kind = __builtin_amdgcn_readfirstlane(B.reqs[req].kind);
+        const GenLaunch& L = B.reqs[req].L;
+        switch (kind) {
+            case kBUniF64x1: batch_tile<kBUniF64x1>(L, sblk, chunk); break;
+            case kBUniF64x2: batch_tile<kBUniF64x2>(L, sblk, chunk); break;
+            case kBUniF32x1: batch_tile<kBUniF32x1>(L, sblk, chunk); break;
+            case kBUniF32x4: batch_tile<kBUniF32x4>(L, sblk, chunk); break;
+            case kBRawU32x1: batch_tile<kBRawU32x1>(L, sblk, chunk); break;
+            case kBRawU32x4: batch_tile<kBRawU32x4>(L, sblk, chunk); break;
+            case kBNormF64: batch_tile<kBNormF64>(L, sblk, chunk); break;
+            case kBNormF32: batch_tile<kBNormF32>(L, sblk, chunk); break;
+            case kBExpF64: batch_tile<kBExpF64>(L, sblk, chunk); break;
+            default: batch_tile<kBExpF32>(L, sblk, chunk); break;
+        }
+        __threadfence();  // this wave's stores are visible before the count
+        const uint32_t left = __builtin_amdgcn_readfirstlane(atomicSub(&B.slots[req].remaining, one));
+        if (left == 1) {  // wave-uniform: this wave finished the request
+            B.slots[req].t_done = __builtin_amdgcn_s_memrealtime();
+            __threadfence();
+            B.slots[req].done = 1;
+        }
+    }
+}
+
+// States of requests split over several chunks: cur <- A^(steps consumed) cur,
+// after every tile has read them.  Thread g -> (request, stream) through the
+// prefix sums of their stream counts.
+__global__ void __launch_bounds__(256) batch_finalize_kernel(BatchLaunch B) {
+    const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= B.fin_total) return;
+    uint32_t lo = 0, hi = B.n_fin;  // largest i with fin_pre[i] <= g
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) / 2;
+        if (B.fin_pre[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    const GenLaunch& L = B.reqs[B.fin_req[lo]].L;
+    const uint32_t s = static_cast<uint32_t>(g - B.fin_pre[lo]);
+    const uint64_t cnt = L.q + (s < L.r ? 1 : 0);
+    const uint64_t steps = L.dist == kNormal ? (cnt + 1) / 2 * 2 : cnt;
+    uint32_t* rec = L.streams + static_cast<uint64_t>(s) * 18;
+    uint32_t x[6];
+#pragma unroll
+    for (int w = 0; w < 6; ++w) x[w] = rec[w];
+    for (int b = 0; b < 64; ++b)
         if ((steps >> b) & 1) dev_apply(g_tab.step_pow2[0][b], g_tab.step_pow2[1][b], x);
 #pragma unroll
     for (int w = 0; w < 6; ++w) rec[w] = x[w];
@@ -632,6 +738,37 @@ static hipError_t launch_gen_only(const GenLaunch& L, hipStream_t s) {
         default:
             return launch_dd<kRaw, kU32>(L, s);
     }
+}
+
+int batch_kind(int dist, int dtype, int spl) {
+    switch (dist) {
+        case kUniform:
+            if (dtype == kF64) return spl == 2 ? kBUniF64x2 : kBUniF64x1;
+            return spl == 4 ? kBUniF32x4 : kBUniF32x1;
+        case kRaw: return spl == 4 ? kBRawU32x4 : kBRawU32x1;
+        case kNormal: return dtype == kF64 ? kBNormF64 : kBNormF32;
+        default: return dtype == kF64 ? kBExpF64 : kBExpF32;
+    }
+}
+
+int device_cu_count() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 256;
+    return cus;
+}
+
+hipError_t launch_batch(const BatchLaunch& B, unsigned grid, unsigned block, hipStream_t s) {
+    hipLaunchKernelGGL(batch_init_kernel, dim3(grid1d(B.n_req ? B.n_req : 1, 256)), dim3(256), 0, s, B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), 0, s, B);
+    e = hipGetLastError();
+    if (e != hipSuccess || B.fin_total == 0) return e;
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3(static_cast<unsigned>((B.fin_total + 255) / 256)),
+                       dim3(256), 0, s, B);
+    return hipGetLastError();
 }
 
 hipError_t launch_generate(const GenLaunch& L, hipStream_t s) {

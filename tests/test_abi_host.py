@@ -178,3 +178,64 @@ def test_export_size():
     sz = ctypes.c_size_t()
     assert P.lib().mrg_streams_export_size(10, 1, ctypes.byref(sz)) == 0
     assert sz.value == 24 + 10 * 72 + 24
+
+
+# ------------------------------------------------------------------ batching
+def _req(streams, S, n, dist=0, dtype=0, rate=1.0, out=4096):
+    return P.mrg_request(streams, S, n, dist, dtype, rate, out)
+
+
+def _plan_status(reqs, cfg=None):
+    arr = (P.mrg_request * max(len(reqs), 1))(*reqs)
+    plan = ctypes.c_void_p()
+    c = None if cfg is None else ctypes.byref(P.mrg_batch_cfg(*cfg))
+    st = P.lib().mrg_batch_plan_create(1, arr, len(reqs), c, ctypes.byref(plan))
+    return st, plan
+
+
+def test_batch_plan_validation():
+    """Plans are built on the host; invalid requests are refused before any
+    device work.  Pointers are never dereferenced here."""
+    base = 1 << 20
+    ok = [_req(base, 64, 64 * 10, out=1 << 30), _req(base + 64 * 72, 64, 640, out=(1 << 30) + 640 * 8)]
+    st, plan = _plan_status(ok)
+    assert st == 0
+    sz, nt = ctypes.c_size_t(), ctypes.c_size_t()
+    assert P.lib().mrg_batch_workspace_size(plan, ctypes.byref(sz)) == 0 and sz.value % 256 == 0
+    assert P.lib().mrg_batch_tile_count(plan, ctypes.byref(nt)) == 0
+    assert nt.value == 2  # 64 streams x 10 draws each: one wave-tile per request (2 streams/lane)
+    P.lib().mrg_batch_plan_destroy(plan)
+    bad_cases = [
+        [_req(base, 64, 640, out=1 << 30), _req(base + 63 * 72, 64, 640, out=(1 << 31))],  # shared streams
+        [_req(base, 64, 640, out=1 << 30), _req(base + 64 * 72, 64, 640, out=(1 << 30) + 8)],  # shared out
+        [_req(base, 64, 640, dist=3, dtype=0)],   # raw needs u32
+        [_req(base, 64, 640, dist=2, rate=0.0)],  # bad rate
+        [_req(base, 0, 640)],                     # no streams
+        [_req(0, 64, 640)],                       # NULL streams
+        [_req(base, 64, 640, out=4097)],          # misaligned output
+    ]
+    for reqs in bad_cases:
+        st, _ = _plan_status(reqs)
+        assert st == -1, reqs
+    st, _ = _plan_status(ok, (0, 17, 0))
+    assert st == -1  # waves_per_simd above 16
+    arr = (P.mrg_request * 1)(*ok[:1])
+    plan = ctypes.c_void_p()
+    assert P.lib().mrg_batch_plan_create(2, arr, 1, None, ctypes.byref(plan)) == -3
+
+
+def test_batch_tiles_cover_requests():
+    """Tile counts follow the cut: ceil(S / (64*SPL)) stream blocks times
+    ceil(units / tile_units) chunks, summed over requests."""
+    base = 1 << 20
+    S1, n1 = 130, 130 * 1000 + 7          # f64 uniform, S even -> 2 streams/lane
+    S2, n2 = 77, 77 * 301                 # normal, 1 stream/lane, pairs = 151
+    reqs = [_req(base, S1, n1, out=1 << 32),
+            _req(base + S1 * 72, S2, n2, dist=1, out=(1 << 33))]
+    st, plan = _plan_status(reqs, (100, 0, 0))
+    assert st == 0
+    nt = ctypes.c_size_t()
+    P.lib().mrg_batch_tile_count(plan, ctypes.byref(nt))
+    want = 2 * ((1001 + 99) // 100) + 2 * ((151 + 99) // 100)
+    assert nt.value == want
+    P.lib().mrg_batch_plan_destroy(plan)
