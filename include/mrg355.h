@@ -210,7 +210,8 @@ typedef struct {
 /* Batch launch shape (0 = automatic for every field).  Results never depend
  * on it.
  *   tile_units      most draws (normal: pairs) one wave makes in one tile
- *   waves_per_simd  resident waves per SIMD of the persistent grid (1..16)
+ *   waves_per_simd  waves per SIMD of the persistent grid (1..16), capped at
+ *                   what the kernel's registers allow to be resident at once
  *   wide_stores     0 = automatic (16-byte stores where a request allows),
  *                   1 = force one stream per lane                        */
 typedef struct {

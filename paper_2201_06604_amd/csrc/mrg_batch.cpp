@@ -32,6 +32,8 @@ struct mrg_batch_plan {
     uint32_t wide;
     std::vector<BatchReq> reqs;
     std::vector<BatchTile> tiles;
+    uint32_t tile_lo[kClasses + 1];
+    double cls_cost[kClasses];
     std::vector<uint32_t> fin_req;
     std::vector<uint64_t> fin_pre;
     uint64_t fin_total;
@@ -48,13 +50,14 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 size_t esz_of(mrg_dtype dt) { return dt == MRG_F64 ? 8 : 4; }
 
-// Estimated VALU cost of one draw unit per stream (uniform steps ~20 ops;
-// the fp64 logarithm, square root and sincospi dominate the transforms).
-double unit_cost(int dist) {
+// Estimated time of one draw unit of one stream, relative units: the whole
+// MI355X runs about 700 G f64 uniforms/s (store-bound), 1.4 T f32 uniforms/s,
+// 325 G normals/s and 300 G exponentials/s (fp64 transcendentals).
+double unit_cost(int dist, int dtype) {
     switch (dist) {
-        case kNormal: return 240.0;
-        case kExponential: return 130.0;
-        default: return 20.0;
+        case kNormal: return 2.0 / 325.0;  // per pair
+        case kExponential: return 1.0 / 300.0;
+        default: return dtype == kF64 ? 1.0 / 700.0 : 1.0 / 1400.0;
     }
 }
 
@@ -136,7 +139,7 @@ mrg_status build(mrg_batch_plan& P) {
                 const uint64_t u = std::min<uint64_t>(chunk, units - j * chunk);
                 P.tiles.push_back(BatchTile{static_cast<uint32_t>(i), static_cast<uint32_t>(sb),
                                             static_cast<uint32_t>(j), 0});
-                cost.push_back(static_cast<double>(u) * unit_cost(L.dist) * spl);
+                cost.push_back(static_cast<double>(u) * unit_cost(L.dist, L.dtype) * 64 * spl);
             }
         if (n_chunks > 1) {
             P.fin_req.push_back(static_cast<uint32_t>(i));
@@ -144,10 +147,23 @@ mrg_status build(mrg_batch_plan& P) {
         }
         P.reqs.push_back(R);
     }
-    // longest first; ties keep request order
+    // grouped by class (normal, exponential, uniform/raw), longest first
+    // within a class; ties keep request order
     std::vector<uint32_t> order(P.tiles.size());
     for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
+    auto cls = [&](uint32_t t) { return batch_kind_class(static_cast<int>(P.reqs[P.tiles[t].req].kind)); };
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        if (cls(a) != cls(b)) return cls(a) < cls(b);
+        return cost[a] > cost[b];
+    });
+    uint32_t n_cls[kClasses] = {0, 0, 0};
+    for (int c = 0; c < kClasses; ++c) P.cls_cost[c] = 0.0;
+    for (uint32_t t = 0; t < P.tiles.size(); ++t) {
+        ++n_cls[cls(t)];
+        P.cls_cost[cls(t)] += cost[t];
+    }
+    P.tile_lo[0] = 0;
+    for (int c = 0; c < kClasses; ++c) P.tile_lo[c + 1] = P.tile_lo[c] + n_cls[c];
     std::vector<BatchTile> sorted(P.tiles.size());
     for (size_t i = 0; i < order.size(); ++i) sorted[i] = P.tiles[order[i]];
     P.tiles.swap(sorted);
@@ -176,6 +192,7 @@ BatchLaunch launch_args(const mrg_batch_plan& P, void* ws) {
     B.n_tiles = static_cast<uint32_t>(P.tiles.size());
     B.n_fin = static_cast<uint32_t>(P.fin_req.size());
     B.fin_total = P.fin_total;
+    for (int c = 0; c <= kClasses; ++c) B.tile_lo[c] = P.tile_lo[c];
     return B;
 }
 
@@ -197,10 +214,27 @@ mrg_status upload(const mrg_batch_plan& P, void* ws, hipStream_t stream) {
 
 mrg_status launch(const mrg_batch_plan& P, void* ws, hipStream_t stream) {
     if (P.tiles.empty() && P.reqs.empty()) return MRG_OK;
-    const BatchLaunch B = launch_args(P, ws);
-    const uint64_t waves = static_cast<uint64_t>(device_cu_count()) * 4 * P.waves_per_simd;
-    const uint64_t need = (P.tiles.size() + kBatchBlock / 64 - 1) / (kBatchBlock / 64);
-    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(waves / (kBatchBlock / 64), need));
+    BatchLaunch B = launch_args(P, ws);
+    // The grid is at most what is resident at once, shared between the class
+    // loops in proportion to the estimated work (a class with tiles gets at
+    // least one block and at most one per 4 of its tiles); blocks move on to
+    // the other classes when their own queue is empty.
+    const uint64_t wpb = kBatchBlock / 64;
+    const uint64_t per_cu = std::min<uint64_t>(static_cast<uint64_t>(batch_blocks_per_cu()),
+                                               std::max<uint64_t>(1, 4 * P.waves_per_simd / wpb));
+    const uint64_t total = std::max<uint64_t>(kClasses, static_cast<uint64_t>(device_cu_count()) * per_cu);
+    double tot_cost = 0.0;
+    for (int c = 0; c < kClasses; ++c) tot_cost += P.cls_cost[c];
+    uint64_t grid = 0;
+    B.block_lo[0] = 0;
+    for (int c = 0; c < kClasses; ++c) {
+        const uint64_t n_t = P.tile_lo[c + 1] - P.tile_lo[c];
+        uint64_t nb = tot_cost > 0 ? static_cast<uint64_t>(total * (P.cls_cost[c] / tot_cost) + 0.5) : 0;
+        nb = std::min<uint64_t>(std::max<uint64_t>(nb, n_t ? 1 : 0), (n_t + wpb - 1) / wpb);
+        grid += nb;
+        B.block_lo[c + 1] = static_cast<uint32_t>(grid);
+    }
+    if (grid == 0) grid = 1;  // no tiles: one block finds every queue empty
     hipError_t e = launch_batch(B, static_cast<unsigned>(grid), kBatchBlock, stream);
     if (e != hipSuccess) return mrg355_fail(MRG_E_HIP, "batch launch: %s", hipGetErrorString(e));
     return MRG_OK;
@@ -311,7 +345,7 @@ mrg_status mrg_batch_autotune(mrg_batch_plan* plan, void* dev_workspace, size_t 
 
     const uint32_t orig_tu = plan->tile_units, orig_w = plan->waves_per_simd;
     const uint32_t tus[] = {1024, 2048, 4096, 8192, 16384};
-    const uint32_t wps[] = {4, 8};
+    const uint32_t wps[] = {2, 4};
     double best_t = 1e30;
     uint32_t best_tu = orig_tu, best_w = orig_w;
     hipEvent_t a = nullptr, b = nullptr;

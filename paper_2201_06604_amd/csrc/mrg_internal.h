@@ -52,10 +52,18 @@ struct BatchSlot {      // per-request counters, reset by every launch
     uint64_t t_done;    // device real-time clock (100 MHz) at completion
 };
 
+// Tile classes: each has its own queue and its own worker loop.
+enum BatchClass { kClsNormal = 0, kClsExp = 1, kClsPlain = 2, kClasses = 3 };
+
+inline int batch_kind_class(int kind) {
+    if (kind == kBNormF64 || kind == kBNormF32) return kClsNormal;
+    if (kind == kBExpF64 || kind == kBExpF32) return kClsExp;
+    return kClsPlain;
+}
+
 struct BatchHeader {    // at workspace offset 0, reset by every launch
-    uint32_t queue;     // next tile to hand out
-    uint32_t started;
-    uint64_t t_start;   // device real-time clock when the first tile was taken
+    uint32_t queue[4];  // next tile to hand out, per class
+    uint64_t t_start;   // device real-time clock when the persistent kernel started
 };
 
 struct BatchLaunch {    // kernel arguments
@@ -66,12 +74,15 @@ struct BatchLaunch {    // kernel arguments
     const uint32_t* fin_req;  // requests split over chunks (state advanced afterwards)
     const uint64_t* fin_pre;  // prefix sums of their stream counts
     uint32_t n_req, n_tiles, n_fin;
+    uint32_t tile_lo[kClasses + 1];   // class c owns tiles [tile_lo[c], tile_lo[c+1])
+    uint32_t block_lo[kClasses + 1];  // and blocks [block_lo[c], block_lo[c+1])
     uint64_t fin_total;
 };
 
 hipError_t launch_batch(const BatchLaunch& B, unsigned grid, unsigned block, hipStream_t s);
 int batch_kind(int dist, int dtype, int spl);
 int device_cu_count();
+int batch_blocks_per_cu();
 hipError_t launch_generate(const GenLaunch& L, hipStream_t s);
 
 hipError_t launch_create(uint32_t* out, uint64_t n, const uint32_t creator[6], hipStream_t s);

@@ -314,31 +314,38 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
 
     if constexpr (DIST == kNormal) {
         // 3 pairs = 6 steps per iteration: the register ring returns home.
-        for (; k + 3 <= kend; k += 3) {
-            Pack<T, SPL> px[3], py[3];
+        // Each pair is transformed and stored as soon as its two steps exist,
+        // which keeps few values live.
+        auto pair = [&](auto z_of) {
+            Pack<T, SPL> px, py;
 #pragma unroll
             for (int i = 0; i < SPL; ++i) {
-                auto z0 = e[i].template step<0>();
-                auto z1 = e[i].template step<1>();
-                auto z2 = e[i].template step<2>();
-                auto z3 = e[i].template step<0>();
-                auto z4 = e[i].template step<1>();
-                auto z5 = e[i].template step<2>();
                 double x, y;
+                z_of(e[i], x, y);
+                px.v[i] = narrow<DTYPE>(x);
+                py.v[i] = narrow<DTYPE>(y);
+            }
+            store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, px);
+            row += rowstep;
+            store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, py);
+            row += rowstep;
+        };
+        for (; k + 3 <= kend; k += 3) {
+            pair([](Engine& g, double& x, double& y) {
+                auto z0 = g.template step<0>();
+                auto z1 = g.template step<1>();
                 box_muller(z0, z1, x, y);
-                px[0].v[i] = narrow<DTYPE>(x); py[0].v[i] = narrow<DTYPE>(y);
+            });
+            pair([](Engine& g, double& x, double& y) {
+                auto z2 = g.template step<2>();
+                auto z3 = g.template step<0>();
                 box_muller(z2, z3, x, y);
-                px[1].v[i] = narrow<DTYPE>(x); py[1].v[i] = narrow<DTYPE>(y);
+            });
+            pair([](Engine& g, double& x, double& y) {
+                auto z4 = g.template step<1>();
+                auto z5 = g.template step<2>();
                 box_muller(z4, z5, x, y);
-                px[2].v[i] = narrow<DTYPE>(x); py[2].v[i] = narrow<DTYPE>(y);
-            }
-#pragma unroll
-            for (int p = 0; p < 3; ++p) {
-                store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, px[p]);
-                row += rowstep;
-                store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, py[p]);
-                row += rowstep;
-            }
+            });
         }
         for (; k < kend; ++k) {
             Pack<T, SPL> px, py;
@@ -465,8 +472,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(uint32_t* streams, uint32
 __global__ void __launch_bounds__(256) batch_init_kernel(BatchLaunch B) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
-        B.head->queue = 0;
-        B.head->started = 0;
+        for (int c = 0; c < 4; ++c) B.head->queue[c] = 0;
         B.head->t_start = 0;
     }
     if (i < B.n_req) {
@@ -490,39 +496,53 @@ __device__ __forceinline__ void batch_tile(const GenLaunch& L, uint32_t sblk, ui
     if constexpr (KIND == kBExpF32) run_chunk<kExponential, kF32, kArithF64, 1, true>(L, sblk, chunk);
 }
 
-// Persistent kernel: every wave takes tiles from one atomic counter until the
-// queue is empty (each wave exits after at most n_tiles + 1 takes).  Tiles
-// were sorted longest first on the host.  After its stores, a wave counts the
-// tile off its request; the wave that finishes a request stamps the device
-// real-time clock into the request's slot.
+// Persistent kernel.  Tiles come in three classes with separate queues:
+// normals, exponentials (both fp64-transcendental heavy) and uniform/raw.
+// Each class has its own loop, which contains only that class's code, so the
+// register budget of the kernel is that of its largest class rather than of
+// all of them together (constants hoisted above a loop stay live for the
+// whole loop).  Within a class, every wave takes
+// tiles from one atomic counter until the class queue is empty (at most
+// (tiles of the class) + 1 takes per wave).  Tiles were sorted longest first
+// on the host.  After its stores, a wave counts the tile off its request; the
+// wave that finishes a request stamps the device real-time clock into the
+// request's slot.
 //
 // No branch on the lane index surrounds the atomics: every lane executes them
 // with an increment of 1 on lane 0 and 0 elsewhere, and the wave takes lane
-// 0's result with readfirstlane.  The loop's control flow is therefore
+// 0's result with readfirstlane.  Each loop's control flow is therefore
 // wave-uniform, and no lane can be left iterating on its own.
-__global__ void __launch_bounds__(256) batch_kernel(BatchLaunch B) {
+template <int CLS>
+__device__ __forceinline__ void batch_worker(const BatchLaunch& B) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t one = lane == 0 ? 1u : 0u;
+    const uint32_t lo = B.tile_lo[CLS];
+    const uint32_t count = B.tile_lo[CLS + 1] - lo;
+    uint32_t* queue = &B.head->queue[CLS];
     for (;;) {
-        const uint32_t t = __builtin_amdgcn_readfirstlane(atomicAdd(&B.head->queue, one));
-        if (t >= B.n_tiles) break;
-        if (t == 0) B.head->t_start = __builtin_amdgcn_s_memrealtime();  // same value from every lane
+        const uint32_t q = __builtin_amdgcn_readfirstlane(atomicAdd(queue, one));
+        if (q >= count) break;
+        const uint32_t t = lo + q;
         const uint32_t req = __builtin_amdgcn_readfirstlane(B.tiles[t].req);
         const uint32_t sblk = __builtin_amdgcn_readfirstlane(B.tiles[t].sblk);
         const uint32_t chunk = __builtin_amdgcn_readfirstlane(B.tiles[t].chunk);
         const uint32_t kind = __builtin_amdgcn_readfirstlane(B.reqs[req].kind);
         const GenLaunch& L = B.reqs[req].L;
-        switch (kind) {
-            case kBUniF64x1: batch_tile<kBUniF64x1>(L, sblk, chunk); break;
-            case kBUniF64x2: batch_tile<kBUniF64x2>(L, sblk, chunk); break;
-            case kBUniF32x1: batch_tile<kBUniF32x1>(L, sblk, chunk); break;
-            case kBUniF32x4: batch_tile<kBUniF32x4>(L, sblk, chunk); break;
-            case kBRawU32x1: batch_tile<kBRawU32x1>(L, sblk, chunk); break;
-            case kBRawU32x4: batch_tile<kBRawU32x4>(L, sblk, chunk); break;
-            case kBNormF64: batch_tile<kBNormF64>(L, sblk, chunk); break;
-            case kBNormF32: batch_tile<kBNormF32>(L, sblk, chunk); break;
-            case kBExpF64: batch_tile<kBExpF64>(L, sblk, chunk); break;
-            default: batch_tile<kBExpF32>(L, sblk, chunk); break;
+        if constexpr (CLS == kClsNormal) {
+            if (kind == kBNormF64) batch_tile<kBNormF64>(L, sblk, chunk);
+            else batch_tile<kBNormF32>(L, sblk, chunk);
+        } else if constexpr (CLS == kClsExp) {
+            if (kind == kBExpF64) batch_tile<kBExpF64>(L, sblk, chunk);
+            else batch_tile<kBExpF32>(L, sblk, chunk);
+        } else {
+            switch (kind) {
+                case kBUniF64x1: batch_tile<kBUniF64x1>(L, sblk, chunk); break;
+                case kBUniF64x2: batch_tile<kBUniF64x2>(L, sblk, chunk); break;
+                case kBUniF32x1: batch_tile<kBUniF32x1>(L, sblk, chunk); break;
+                case kBUniF32x4: batch_tile<kBUniF32x4>(L, sblk, chunk); break;
+                case kBRawU32x1: batch_tile<kBRawU32x1>(L, sblk, chunk); break;
+                default: batch_tile<kBRawU32x4>(L, sblk, chunk); break;
+            }
         }
         __threadfence();  // this wave's stores are visible before the count
         const uint32_t left = __builtin_amdgcn_readfirstlane(atomicSub(&B.slots[req].remaining, one));
@@ -531,6 +551,26 @@ __global__ void __launch_bounds__(256) batch_kernel(BatchLaunch B) {
             __threadfence();
             B.slots[req].done = 1;
         }
+    }
+}
+
+// A block starts on its own class (blocks are shared out by estimated work),
+// then helps the other classes until every queue is empty.  The three loops
+// run one after another, so their register live ranges never overlap.
+__global__ void __launch_bounds__(256) batch_kernel(BatchLaunch B) {
+    if (blockIdx.x == 0 && threadIdx.x < 64) B.head->t_start = __builtin_amdgcn_s_memrealtime();
+    if (blockIdx.x < B.block_lo[1]) {
+        batch_worker<kClsNormal>(B);
+        batch_worker<kClsExp>(B);
+        batch_worker<kClsPlain>(B);
+    } else if (blockIdx.x < B.block_lo[2]) {
+        batch_worker<kClsExp>(B);
+        batch_worker<kClsNormal>(B);
+        batch_worker<kClsPlain>(B);
+    } else {
+        batch_worker<kClsPlain>(B);
+        batch_worker<kClsNormal>(B);
+        batch_worker<kClsExp>(B);
     }
 }
 
@@ -749,6 +789,18 @@ int batch_kind(int dist, int dtype, int spl) {
         case kNormal: return dtype == kF64 ? kBNormF64 : kBNormF32;
         default: return dtype == kF64 ? kBExpF64 : kBExpF32;
     }
+}
+
+// Blocks of the persistent batch kernel that fit on one CU at once.
+int batch_blocks_per_cu() {
+    static int cached = 0;
+    if (cached) return cached;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(batch_kernel), 256, 0) !=
+            hipSuccess || n <= 0)
+        n = 1;
+    cached = n;
+    return n;
 }
 
 int device_cu_count() {

@@ -188,7 +188,7 @@ def test_batch_autotune_leaves_streams_and_stays_exact():
     plan.upload()
     before = [t.clone() for t in A.streams]
     best, ms = plan.autotune()
-    assert best["tile_units"] in (1024, 2048, 4096, 8192, 16384) and ms > 0
+    assert best["tile_units"] in (1024, 2048, 4096, 8192, 16384) and best["waves_per_simd"] in (2, 4) and ms > 0
     for a, b in zip(A.streams, before):
         assert torch.equal(a, b)
     plan.launch()
