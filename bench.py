@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
     ap.add_argument("--no-variants", action="store_true", help="skip f32/normal/exponential timings")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
@@ -112,6 +113,88 @@ def cpu_baseline(seed):
     return {"value": n / dt / 1e9, "unit": "GSamples/s", "cores": threads, "kind": "oracle",
             "sample": f"{S_sample} streams x {PER_STREAM} fp64 uniforms, the whole workload "
                       f"({n} draws, {dt:.2f} s wall on {threads} threads)"}
+
+
+def bench_batched(torch, P, workloads, reps=3):
+    """4,096 generation requests (lengths log-uniform in [1e3, 1e7], 64-1,024
+    streams each, random f32/f64 x uniform/normal/exponential) on consecutive
+    streams of one creator: 4,096 back-to-back plain launches against one
+    autotuned persistent launch replayed from a HIP graph.  Per-request
+    latency = completion time from the start of the run (plain: HIP events
+    after each launch; batched: device completion stamps)."""
+    reqs = workloads.batch_requests()
+    total_S = sum(r["n_streams"] for r in reqs)
+    total_n = sum(r["n"] for r in reqs)
+    c = P.mrg_creator_init(workloads.random_seed())
+    streams = P.mrg_streams_create_device(c, total_S)
+    dmap = {0: P.MRG_UNIFORM, 1: P.MRG_NORMAL, 2: P.MRG_EXPONENTIAL}
+    tmap = {0: (P.MRG_F64, torch.float64), 1: (P.MRG_F32, torch.float32)}
+    meta, creqs = [], []
+    for r in reqs:
+        dist = dmap[r["dist"]]
+        dtype, tdt = tmap[r["dtype"]]
+        s = streams[r["first_stream"]:r["first_stream"] + r["n_streams"]]
+        o = torch.empty(r["n"], dtype=tdt, device="cuda")
+        meta.append((s, r["n"], dist, dtype, o))
+        creqs.append(P.make_request(s, r["n"], dist, dtype, 1.0, o))
+    out_bytes = sum(m[4].numel() * m[4].element_size() for m in meta)
+
+    def plain_once():
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(meta) + 1)]
+        evs[0].record()
+        for i, (s, n, dist, dtype, o) in enumerate(meta):
+            P.mrg_generate(s, n, dist, dtype, 1.0, out=o)
+            evs[i + 1].record()
+        torch.cuda.synchronize()
+        return np.array([evs[0].elapsed_time(e) for e in evs[1:]])
+
+    plain_once()
+    runs = [plain_once() for _ in range(reps)]
+    lat_p = min(runs, key=lambda a: a[-1])
+
+    tune = P.BatchPlan(creqs, dict(tile_units=1024))
+    plan = P.BatchPlan(creqs)
+    plan.alloc_workspace(max(tune.workspace_size(), plan.workspace_size()))
+    del tune
+    plan.upload()
+    best, _ = plan.autotune()
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    with torch.cuda.graph(g, stream=st):
+        plan.launch(stream=st.cuda_stream)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    best_ms, lat_b = None, None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        t = plan.request_times()
+        lat = (t[1:].astype(np.float64) - float(t[0])) * 1e-5  # 100 MHz ticks -> ms
+        if best_ms is None or ms < best_ms:
+            best_ms, lat_b = ms, lat
+    del g
+
+    def stats(ms, lat):
+        return {"makespan_ms": round(float(ms), 3), "GSamples_per_s": round(total_n / (ms * 1e-3) / 1e9, 2),
+                "GB_per_s": round(out_bytes / (ms * 1e-3) / 1e9, 1),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+
+    res = {"workload": "4096 requests, lengths log-uniform in [1e3, 1e7], 64-1024 streams each, "
+                       "random f32/f64 x uniform/normal/exponential(rate 1)",
+           "requests": len(reqs), "streams": total_S, "draws": total_n, "output_bytes": out_bytes,
+           "plain": stats(lat_p[-1], lat_p), "batched": stats(best_ms, lat_b),
+           "batched_tuning": best}
+    res["speedup_makespan"] = round(res["plain"]["makespan_ms"] / res["batched"]["makespan_ms"], 2)
+    res["p99_ratio_plain_over_batched"] = round(res["plain"]["p99_ms"] / res["batched"]["p99_ms"], 2)
+    for m in meta:
+        del m
+    return res
 
 
 def main():
@@ -221,6 +304,9 @@ def main():
                          "GB_per_s": round(N * esz / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4)}
         del out32
         res["variants"] = var
+
+    if not args.no_batch:
+        res["batched"] = bench_batched(torch, P, workloads)
 
     if args.copy_probe:
         a = torch.empty(COPY_PROBE_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)

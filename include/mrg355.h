@@ -261,6 +261,89 @@ mrg_status mrg_batch_request_times(const mrg_batch_plan* plan, const void* dev_w
 mrg_status mrg_batch_autotune(mrg_batch_plan* plan, void* dev_workspace, size_t workspace_bytes,
                               hipStream_t stream, mrg_batch_cfg* best, double* best_ms);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over sessions whose stream state stays on the
+ * device.  Section 2.1 keeps streams explicit and on the GPU so that
+ * interrupted and restored sessions stay reproducible; the server keeps each
+ * session's streams resident and assigns every request its position in the
+ * session's sequence when it arrives.
+ *
+ *   - Session i owns streams_per_session streams created from `seed` (session
+ *     i takes streams i*S .. i*S+S-1 of one creator).  A request of n draws
+ *     on a session uses all its S streams: draw k of stream s is element
+ *     k*S + s of the request's output, exactly as mrg_generate lays it out.
+ *   - Positions are assigned at submission, in submission order: a request
+ *     starts where the session's previous request ended, and advances every
+ *     stream of the session by ceil(n/S) steps (normals: rounded up to even).
+ *     Its numbers are those mrg_generate gives for the session's streams
+ *     advanced to that position, whatever else is running.
+ *   - Requests are admitted in submission order as output memory in the pool
+ *     frees up, batched as they arrive into persistent launches (up to
+ *     `lanes` of them in flight on separate HIP streams, overlapping on the
+ *     device), and completed individually: the kernel flags each request in
+ *     host-visible memory when its output is stored.
+ *   - mode 1 replaces batching by one plain launch per request at admission,
+ *     in submission order on one HIP stream (the comparison baseline).
+ * mrg_server_create allocates the session streams, the per-lane workspaces
+ * (device) and the completion flags and staging buffers (pinned host
+ * memory), and starts one scheduler thread; nothing is allocated afterwards.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint32_t n_sessions;
+    uint32_t streams_per_session;  /* 0 = 64 */
+    uint32_t seed[6];
+    void* pool;                    /* device memory for request outputs (caller-owned) */
+    size_t pool_bytes;
+    uint32_t lanes;                /* launches in flight at once (0 = 4) */
+    uint32_t max_batch;            /* requests per launch at most (0 = 256) */
+    uint32_t mode;                 /* 0 = continuous batching, 1 = one plain launch per request */
+    uint32_t tile_units;           /* 0 = 2048 */
+} mrg_server_cfg;
+
+typedef struct {
+    uint64_t submitted, completed, released, rejected;
+    uint64_t samples_completed;
+    uint64_t launches;             /* batches (mode 0) or plain launches (mode 1) */
+    uint64_t pool_in_use, pool_peak;
+    uint64_t max_in_flight;        /* most requests on the device at once */
+} mrg_server_stats;
+
+typedef struct mrg_server mrg_server;  /* opaque */
+
+uint64_t   mrg_now_ns(void);           /* the steady clock the server uses */
+mrg_status mrg_server_create(const mrg_server_cfg* cfg, mrg_server** srv);
+void       mrg_server_destroy(mrg_server* srv);  /* waits for work in flight */
+
+/* Queue a request (thread-safe, never blocks on the GPU).  `t_arrival_ns`
+ * (mrg_now_ns clock) is when the request arrived; latency is measured from
+ * it.  MRG_E_NOMEM when the output alone exceeds the pool (nothing queued,
+ * no position assigned).  *ticket identifies the request; *offset_out
+ * (optional) receives its starting position in the session. */
+mrg_status mrg_server_submit(mrg_server* srv, uint32_t session, uint64_t n, mrg_dist dist,
+                             mrg_dtype dtype, double param, uint64_t t_arrival_ns, uint64_t* ticket,
+                             uint64_t* offset_out);
+
+/* Non-blocking query: *done = 1 once the output is in the pool; then
+ * *dev_out points at it (n elements) and *t_done_ns is when the server saw
+ * it complete. */
+mrg_status mrg_server_poll(mrg_server* srv, uint64_t ticket, int* done, void** dev_out,
+                           uint64_t* t_done_ns);
+
+/* Give the output memory of a completed request back to the pool. */
+mrg_status mrg_server_release(mrg_server* srv, uint64_t ticket);
+
+mrg_status mrg_server_stats_get(mrg_server* srv, mrg_server_stats* out);
+
+/* Open-loop replay on the calling thread: request i (session[i], n_draws[i]
+ * draws of dist/dtype/param) arrives t_arrival_ns[i] after the start; it is
+ * submitted at that time, and released as soon as it completes.  Fills
+ * latency_ns[i] (completion seen - arrival) and *span_ns (start to the last
+ * completion).  Returns when every request has completed. */
+mrg_status mrg_server_drive(mrg_server* srv, size_t n, const uint64_t* t_arrival_ns,
+                            const uint32_t* session, const uint64_t* n_draws, mrg_dist dist,
+                            mrg_dtype dtype, double param, uint64_t* latency_ns, uint64_t* span_ns);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,6 +64,19 @@ class mrg_batch_cfg(ctypes.Structure):
                 ("wide_stores", ctypes.c_uint32)]
 
 
+class mrg_server_cfg(ctypes.Structure):
+    _fields_ = [("n_sessions", ctypes.c_uint32), ("streams_per_session", ctypes.c_uint32),
+                ("seed", ctypes.c_uint32 * 6), ("pool", ctypes.c_void_p), ("pool_bytes", ctypes.c_size_t),
+                ("lanes", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("mode", ctypes.c_uint32),
+                ("tile_units", ctypes.c_uint32)]
+
+
+class mrg_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "released", "rejected",
+                                                "samples_completed", "launches", "pool_in_use",
+                                                "pool_peak", "max_in_flight")]
+
+
 _lib = None
 
 
@@ -105,6 +118,17 @@ def lib():
             "mrg_batch_request_times": (i32, [vp, vp, ctypes.POINTER(ctypes.c_uint64), vp]),
             "mrg_batch_autotune": (i32, [vp, vp, sz, vp, ctypes.POINTER(mrg_batch_cfg),
                                          ctypes.POINTER(ctypes.c_double)]),
+            "mrg_now_ns": (u64, []),
+            "mrg_server_create": (i32, [ctypes.POINTER(mrg_server_cfg), ctypes.POINTER(vp)]),
+            "mrg_server_destroy": (None, [vp]),
+            "mrg_server_submit": (i32, [vp, ctypes.c_uint32, u64, i32, i32, ctypes.c_double, u64,
+                                        ctypes.POINTER(u64), ctypes.POINTER(u64)]),
+            "mrg_server_poll": (i32, [vp, u64, ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(u64)]),
+            "mrg_server_release": (i32, [vp, u64]),
+            "mrg_server_stats_get": (i32, [vp, ctypes.POINTER(mrg_server_stats)]),
+            "mrg_server_drive": (i32, [vp, sz, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_uint32),
+                                       ctypes.POINTER(u64), i32, i32, ctypes.c_double,
+                                       ctypes.POINTER(u64), ctypes.POINTER(u64)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -120,7 +144,9 @@ EXPORTED = ["mrg_abi_version", "mrg_status_string", "mrg_last_error", "mrg_seed_
             "mrg_streams_export_size", "mrg_streams_export", "mrg_streams_import",
             "mrg_batch_plan_create", "mrg_batch_plan_destroy", "mrg_batch_workspace_size",
             "mrg_batch_tile_count", "mrg_batch_upload", "mrg_batch_launch",
-            "mrg_batch_request_times", "mrg_batch_autotune"]
+            "mrg_batch_request_times", "mrg_batch_autotune", "mrg_now_ns", "mrg_server_create",
+            "mrg_server_destroy", "mrg_server_submit", "mrg_server_poll", "mrg_server_release",
+            "mrg_server_stats_get", "mrg_server_drive"]
 
 
 def _check(st):
@@ -339,3 +365,80 @@ class BatchPlan:
                                         _stream(stream), ctypes.byref(best), ctypes.byref(ms)))
         return dict(tile_units=best.tile_units, waves_per_simd=best.waves_per_simd,
                     wide_stores=best.wide_stores), ms.value
+
+
+# ------------------------------------------------------------------ serving
+def mrg_now_ns():
+    return lib().mrg_now_ns()
+
+
+class Server:
+    """Owns an mrg_server.  `pool` is a device tensor the outputs live in."""
+
+    def __init__(self, n_sessions, seed, pool, streams_per_session=0, lanes=0, max_batch=0, mode=0,
+                 tile_units=0):
+        cfg = mrg_server_cfg()
+        cfg.n_sessions = n_sessions
+        cfg.streams_per_session = streams_per_session
+        for i, v in enumerate(_seed_arr(seed)):
+            cfg.seed[i] = int(v)
+        self.pool = pool
+        cfg.pool = pool.data_ptr()
+        cfg.pool_bytes = pool.numel() * pool.element_size()
+        cfg.lanes, cfg.max_batch, cfg.mode, cfg.tile_units = lanes, max_batch, mode, tile_units
+        self._s = ctypes.c_void_p()
+        _check(lib().mrg_server_create(ctypes.byref(cfg), ctypes.byref(self._s)))
+        self.S = streams_per_session or 64
+
+    def close(self):
+        if getattr(self, "_s", None) and self._s.value:
+            lib().mrg_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        if _lib is not None:
+            self.close()
+
+    def submit(self, session, n, dist=MRG_NORMAL, dtype=MRG_F64, param=1.0, t_arrival_ns=None):
+        t = ctypes.c_uint64()
+        off = ctypes.c_uint64()
+        arr = mrg_now_ns() if t_arrival_ns is None else t_arrival_ns
+        _check(lib().mrg_server_submit(self._s, session, n, dist, dtype, param, arr, ctypes.byref(t),
+                                       ctypes.byref(off)))
+        return t.value, off.value
+
+    def submit_status(self, session, n, dist=MRG_NORMAL, dtype=MRG_F64, param=1.0):
+        t = ctypes.c_uint64()
+        return lib().mrg_server_submit(self._s, session, n, dist, dtype, param, mrg_now_ns(), ctypes.byref(t),
+                                       None)
+
+    def poll(self, ticket):
+        """(done, device address of the output, completion time ns)."""
+        d = ctypes.c_int()
+        p = ctypes.c_void_p()
+        t = ctypes.c_uint64()
+        _check(lib().mrg_server_poll(self._s, ticket, ctypes.byref(d), ctypes.byref(p), ctypes.byref(t)))
+        return bool(d.value), p.value, t.value
+
+    def release(self, ticket):
+        _check(lib().mrg_server_release(self._s, ticket))
+
+    def stats(self):
+        st = mrg_server_stats()
+        _check(lib().mrg_server_stats_get(self._s, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def drive(self, t_arrival_ns, sessions, n_draws, dist=MRG_NORMAL, dtype=MRG_F64, param=1.0):
+        """Open-loop replay; returns (latency_ns array, span_ns)."""
+        n = len(t_arrival_ns)
+        ta = np.ascontiguousarray(t_arrival_ns, dtype=np.uint64)
+        se = np.ascontiguousarray(sessions, dtype=np.uint32)
+        nd = np.ascontiguousarray(n_draws, dtype=np.uint64)
+        lat = np.zeros(n, dtype=np.uint64)
+        span = ctypes.c_uint64()
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        _check(lib().mrg_server_drive(self._s, n, ta.ctypes.data_as(u64p),
+                                      se.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                      nd.ctypes.data_as(u64p), dist, dtype, param, lat.ctypes.data_as(u64p),
+                                      ctypes.byref(span)))
+        return lat, span.value

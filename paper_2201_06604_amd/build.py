@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmrg355.so")
-SOURCES = ["mrg_kernels.hip", "mrg_api.cpp", "mrg_batch.cpp"]
+SOURCES = ["mrg_kernels.hip", "mrg_api.cpp", "mrg_batch.cpp", "mrg_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -41,7 +41,7 @@ def build(verbose: bool = False) -> str:
         _compile(src, obj, extra)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs,
+    subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs,
                    check=True, cwd=CSRC)
     os.replace(tmp, LIB)
     return LIB

@@ -26,7 +26,7 @@ mrg_status mrg355_fail(mrg_status st, const char* fmt, ...);  // mrg_api.cpp
 
 struct mrg_batch_plan {
     mrg_generator gen;
-    std::vector<mrg_request> user;
+    std::vector<mrg355::PlanReq> user;
     uint32_t tile_units;
     uint32_t waves_per_simd;
     uint32_t wide;
@@ -99,9 +99,11 @@ mrg_status build(mrg_batch_plan& P) {
     P.fin_pre.assign(1, 0);
     std::vector<double> cost;
     for (size_t i = 0; i < P.user.size(); ++i) {
-        const mrg_request& q = P.user[i];
+        const mrg_request& q = P.user[i].q;
         BatchReq R{};
         GenLaunch& L = R.L;
+        L.offset = P.user[i].offset;
+        L.no_writeback = P.user[i].no_writeback;
         L.streams = reinterpret_cast<uint32_t*>(q.streams);
         L.out = q.out;
         L.dist = static_cast<int>(q.dist);
@@ -141,7 +143,7 @@ mrg_status build(mrg_batch_plan& P) {
                                             static_cast<uint32_t>(j), 0});
                 cost.push_back(static_cast<double>(u) * unit_cost(L.dist, L.dtype) * 64 * spl);
             }
-        if (n_chunks > 1) {
+        if (n_chunks > 1 && !L.no_writeback) {
             P.fin_req.push_back(static_cast<uint32_t>(i));
             P.fin_pre.push_back(P.fin_pre.back() + L.S);
         }
@@ -196,15 +198,21 @@ BatchLaunch launch_args(const mrg_batch_plan& P, void* ws) {
     return B;
 }
 
-mrg_status upload(const mrg_batch_plan& P, void* ws, hipStream_t stream) {
-    std::vector<char> host(P.bytes - P.off_reqs, 0);
+// Static tables of a plan, laid out as in the workspace from off_reqs on.
+void pack_tables(const mrg_batch_plan& P, char* host) {
+    std::memset(host, 0, P.bytes - P.off_reqs);
     auto put = [&](size_t off, const void* src, size_t n) {
-        if (n) std::memcpy(host.data() + (off - P.off_reqs), src, n);
+        if (n) std::memcpy(host + (off - P.off_reqs), src, n);
     };
     put(P.off_reqs, P.reqs.data(), P.reqs.size() * sizeof(BatchReq));
     put(P.off_tiles, P.tiles.data(), P.tiles.size() * sizeof(BatchTile));
     put(P.off_fin_req, P.fin_req.data(), P.fin_req.size() * sizeof(uint32_t));
     put(P.off_fin_pre, P.fin_pre.data(), P.fin_pre.size() * sizeof(uint64_t));
+}
+
+mrg_status upload(const mrg_batch_plan& P, void* ws, hipStream_t stream) {
+    std::vector<char> host(P.bytes - P.off_reqs);
+    pack_tables(P, host.data());
     hipError_t e = hipMemcpyAsync(static_cast<char*>(ws) + P.off_reqs, host.data(), host.size(),
                                   hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -212,9 +220,10 @@ mrg_status upload(const mrg_batch_plan& P, void* ws, hipStream_t stream) {
     return MRG_OK;
 }
 
-mrg_status launch(const mrg_batch_plan& P, void* ws, hipStream_t stream) {
+mrg_status launch(const mrg_batch_plan& P, void* ws, hipStream_t stream, BatchSlot* host_slots = nullptr) {
     if (P.tiles.empty() && P.reqs.empty()) return MRG_OK;
     BatchLaunch B = launch_args(P, ws);
+    B.host_slots = host_slots;
     // The grid is at most what is resident at once, shared between the class
     // loops in proportion to the estimated work (a class with tiles gets at
     // least one block and at most one per 4 of its tiles); blocks move on to
@@ -242,6 +251,37 @@ mrg_status launch(const mrg_batch_plan& P, void* ws, hipStream_t stream) {
 
 }  // namespace
 
+namespace mrg355 {
+
+// Plans for the serving engine: requests already validated, optionally
+// starting at an offset and leaving their streams untouched.
+mrg_status plan_internal(const std::vector<PlanReq>& reqs, uint32_t tile_units, mrg_batch_plan** out) {
+    mrg_batch_plan* P = new (std::nothrow) mrg_batch_plan();
+    if (!P) return mrg355_fail(MRG_E_NOMEM, "plan allocation failed");
+    P->gen = MRG_GEN_MRG32K3A;
+    P->user = reqs;
+    P->tile_units = tile_units;
+    P->waves_per_simd = 4;
+    P->wide = 0;
+    mrg_status st = build(*P);
+    if (st) {
+        delete P;
+        return st;
+    }
+    *out = P;
+    return MRG_OK;
+}
+
+size_t plan_bytes(const mrg_batch_plan* P) { return P->bytes; }
+size_t plan_table_offset(const mrg_batch_plan* P) { return P->off_reqs; }
+void plan_pack_tables(const mrg_batch_plan* P, char* host) { pack_tables(*P, host); }
+
+mrg_status plan_launch(const mrg_batch_plan* P, void* ws, BatchSlot* host_slots, hipStream_t stream) {
+    return launch(*P, ws, stream, host_slots);
+}
+
+}  // namespace mrg355
+
 extern "C" {
 
 mrg_status mrg_batch_plan_create(mrg_generator gen, const mrg_request* reqs, size_t n_req,
@@ -267,7 +307,8 @@ mrg_status mrg_batch_plan_create(mrg_generator gen, const mrg_request* reqs, siz
     mrg_batch_plan* P = new (std::nothrow) mrg_batch_plan();
     if (!P) return mrg355_fail(MRG_E_NOMEM, "plan allocation failed");
     P->gen = gen;
-    P->user.assign(reqs, reqs + n_req);
+    P->user.resize(n_req);
+    for (size_t i = 0; i < n_req; ++i) P->user[i] = PlanReq{reqs[i], 0, 0};
     P->tile_units = (cfg && cfg->tile_units) ? cfg->tile_units : kDefaultTileUnits;
     P->waves_per_simd = (cfg && cfg->waves_per_simd) ? cfg->waves_per_simd : kDefaultWavesPerSimd;
     P->wide = cfg ? cfg->wide_stores : 0;
@@ -335,7 +376,7 @@ mrg_status mrg_batch_autotune(mrg_batch_plan* plan, void* dev_workspace, size_t 
     std::vector<std::vector<char>> saved(plan->user.size());
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < plan->user.size() && e == hipSuccess; ++i) {
-        const mrg_request& q = plan->user[i];
+        const mrg_request& q = plan->user[i].q;
         if (!q.n) continue;
         saved[i].resize(static_cast<size_t>(q.n_streams) * sizeof(mrg_stream));
         e = hipMemcpyAsync(saved[i].data(), q.streams, saved[i].size(), hipMemcpyDeviceToHost, stream);
@@ -380,7 +421,7 @@ mrg_status mrg_batch_autotune(mrg_batch_plan* plan, void* dev_workspace, size_t 
     // restore the streams, keep the best shape
     for (size_t i = 0; i < plan->user.size() && e == hipSuccess; ++i) {
         if (saved[i].empty()) continue;
-        e = hipMemcpyAsync(plan->user[i].streams, saved[i].data(), saved[i].size(), hipMemcpyHostToDevice,
+        e = hipMemcpyAsync(plan->user[i].q.streams, saved[i].data(), saved[i].size(), hipMemcpyHostToDevice,
                            stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);

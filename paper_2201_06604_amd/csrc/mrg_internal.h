@@ -5,6 +5,8 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace mrg355 {
 
 enum Dist { kUniform = 0, kNormal = 1, kExponential = 2, kRaw = 3 };
@@ -24,6 +26,8 @@ struct GenLaunch {
     int dist, dtype, arith, block, nontemporal;
     int spl;             // streams per lane (1, 2, 4); 0 = automatic
     int xcd;             // 1 = XCD-contiguous block order
+    uint64_t offset;     // steps every stream is advanced before its first draw
+    int no_writeback;    // 1 = leave the stream records untouched (served requests)
 };
 
 // Resolve chunk/n_chunks/block/arith left at 0 to the automatic choice.
@@ -69,6 +73,7 @@ struct BatchHeader {    // at workspace offset 0, reset by every launch
 struct BatchLaunch {    // kernel arguments
     BatchHeader* head;
     BatchSlot* slots;
+    BatchSlot* host_slots;    // optional copy of done/t_done in host-mapped memory
     const BatchReq* reqs;
     const BatchTile* tiles;
     const uint32_t* fin_req;  // requests split over chunks (state advanced afterwards)
@@ -80,6 +85,25 @@ struct BatchLaunch {    // kernel arguments
 };
 
 hipError_t launch_batch(const BatchLaunch& B, unsigned grid, unsigned block, hipStream_t s);
+
+}  // namespace mrg355
+
+#include "mrg355.h"
+
+namespace mrg355 {
+
+// A request of a plan: the public request plus where its streams start.
+struct PlanReq {
+    mrg_request q;
+    uint64_t offset;    // steps each stream advances before its first draw
+    int no_writeback;   // 1 = do not write the stream records back
+};
+
+mrg_status plan_internal(const std::vector<PlanReq>& reqs, uint32_t tile_units, mrg_batch_plan** out);
+size_t plan_bytes(const mrg_batch_plan* P);
+size_t plan_table_offset(const mrg_batch_plan* P);
+void plan_pack_tables(const mrg_batch_plan* P, char* host);
+mrg_status plan_launch(const mrg_batch_plan* P, void* ws, BatchSlot* host_slots, hipStream_t stream);
 int batch_kind(int dist, int dtype, int spl);
 int device_cu_count();
 int batch_blocks_per_cu();

@@ -299,7 +299,8 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
         uint32_t x[6];
 #pragma unroll
         for (int w = 0; w < 6; ++w) x[w] = rec[w];
-        if (u0) dev_jump(x, u0 * kSpu);
+        const uint64_t jump = L.offset + u0 * kSpu;
+        if (jump) dev_jump(x, jump);
         e[i].load(x);
     }
 
@@ -417,7 +418,7 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
     // A stream owned by a single work-item is written back here; otherwise
     // finalize_kernel advances it after this launch (other chunks of the same
     // stream may not have read it yet).
-    if (L.n_chunks == 1) {
+    if (L.n_chunks == 1 && !L.no_writeback) {
 #pragma unroll
         for (int i = 0; i < SPL; ++i) {
             uint32_t x[6];
@@ -547,9 +548,15 @@ __device__ __forceinline__ void batch_worker(const BatchLaunch& B) {
         __threadfence();  // this wave's stores are visible before the count
         const uint32_t left = __builtin_amdgcn_readfirstlane(atomicSub(&B.slots[req].remaining, one));
         if (left == 1) {  // wave-uniform: this wave finished the request
-            B.slots[req].t_done = __builtin_amdgcn_s_memrealtime();
+            const uint64_t t_done = __builtin_amdgcn_s_memrealtime();
+            B.slots[req].t_done = t_done;
             __threadfence();
             B.slots[req].done = 1;
+            if (B.host_slots) {  // tell a polling host thread
+                B.host_slots[req].t_done = t_done;
+                __threadfence_system();
+                B.host_slots[req].done = 1;
+            }
         }
     }
 }
@@ -826,7 +833,7 @@ hipError_t launch_batch(const BatchLaunch& B, unsigned grid, unsigned block, hip
 hipError_t launch_generate(const GenLaunch& L, hipStream_t s) {
     if (L.n_chunks == 0) return hipSuccess;
     hipError_t e = launch_gen_only(L, s);
-    if (e != hipSuccess || L.n_chunks == 1) return e;
+    if (e != hipSuccess || L.n_chunks == 1 || L.no_writeback) return e;
     hipLaunchKernelGGL(finalize_kernel, dim3(grid1d(L.S, 256)), dim3(256), 0, s, L.streams, L.S, L.q,
                        L.r, L.dist == kNormal ? 1 : 0);
     return hipGetLastError();

@@ -239,3 +239,27 @@ def test_batch_tiles_cover_requests():
     want = 2 * ((1001 + 99) // 100) + 2 * ((151 + 99) // 100)
     assert nt.value == want
     P.lib().mrg_batch_plan_destroy(plan)
+
+
+# ------------------------------------------------------------------ serving
+def test_server_create_validation():
+    """Server configuration errors are refused before any device work."""
+    L = P.lib()
+    srv = ctypes.c_void_p()
+    assert L.mrg_server_create(None, ctypes.byref(srv)) == -1
+
+    def cfg(**kw):
+        c = P.mrg_server_cfg()
+        c.n_sessions = kw.get("n_sessions", 4)
+        for i in range(6):
+            c.seed[i] = kw.get("seed", [12345] * 6)[i]
+        c.pool = kw.get("pool", 1 << 20)
+        c.pool_bytes = kw.get("pool_bytes", 1 << 20)
+        c.mode = kw.get("mode", 0)
+        c.lanes = kw.get("lanes", 0)
+        c.streams_per_session = kw.get("sps", 0)
+        return c
+    for bad in [dict(n_sessions=0), dict(pool=0), dict(pool_bytes=16), dict(pool=(1 << 20) + 8),
+                dict(mode=2), dict(lanes=65), dict(sps=70000)]:
+        assert L.mrg_server_create(ctypes.byref(cfg(**bad)), ctypes.byref(srv)) == -1, bad
+    assert L.mrg_server_create(ctypes.byref(cfg(seed=[0, 0, 0, 1, 1, 1])), ctypes.byref(srv)) == -2

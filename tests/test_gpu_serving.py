@@ -1,0 +1,163 @@
+"""GPU tests of the serving engine: every served request equals the same
+request generated alone (plain mrg_generate on the session's streams
+advanced to the position the server assigned), whatever was in the mix;
+admission waits for memory instead of failing; the open-loop driver completes
+every request."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2201_06604_amd as P  # noqa: E402
+
+TDT = {P.MRG_F64: torch.float64, P.MRG_F32: torch.float32, P.MRG_U32: torch.int32}
+ESZ = {P.MRG_F64: 8, P.MRG_F32: 4, P.MRG_U32: 4}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def session_records(seed, n_sessions, S=64):
+    c = P.mrg_creator_init(seed)
+    return P.mrg_streams_create_host(c, n_sessions * S)
+
+
+def alone(records, session, offset, n, dist, dtype, param, S=64):
+    """The request by itself: a fresh copy of the session's streams, advanced
+    to the assigned position, then one plain launch."""
+    rec = records[session * S:(session + 1) * S]
+    d = torch.from_numpy(rec.view(np.int32).copy()).cuda()
+    if offset:
+        P.mrg_streams_advance(d, offset)
+    return P.mrg_generate(d, n, dist, dtype, param)
+
+
+def wait_all(srv, tickets, timeout=60.0):
+    t0 = time.time()
+    pending = set(tickets)
+    while pending:
+        for tk in list(pending):
+            done, addr, _ = srv.poll(tk)
+            if done:
+                pending.discard(tk)
+        assert time.time() - t0 < timeout, f"{len(pending)} requests not done"
+        time.sleep(0.001)
+
+
+def mix(rng, n_req, n_sessions):
+    kinds = [(P.MRG_NORMAL, P.MRG_F64, 1.0), (P.MRG_NORMAL, P.MRG_F32, 1.0), (P.MRG_UNIFORM, P.MRG_F64, 1.0),
+             (P.MRG_UNIFORM, P.MRG_F32, 1.0), (P.MRG_EXPONENTIAL, P.MRG_F64, 2.0), (P.MRG_RAW, P.MRG_U32, 1.0)]
+    out = []
+    for _ in range(n_req):
+        k = kinds[rng.integers(0, len(kinds))]
+        n = int(10 ** rng.uniform(0, 5.3))
+        out.append((int(rng.integers(0, n_sessions)), max(n, 1)) + k)
+    return out
+
+
+@pytest.mark.parametrize("mode,lanes,max_batch", [(0, 4, 64), (0, 2, 7), (1, 0, 0)])
+def test_served_equals_alone(mode, lanes, max_batch):
+    n_sessions = 12
+    seed = workloads.random_seed(55)
+    pool = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    srv = P.Server(n_sessions, seed, pool, lanes=lanes, max_batch=max_batch, mode=mode)
+    rng = np.random.default_rng(9 + mode)
+    reqs = mix(rng, 150, n_sessions)
+    tickets = []
+    for sess, n, dist, dtype, param in reqs:
+        tk, off = srv.submit(sess, n, dist, dtype, param)
+        tickets.append((tk, off))
+    wait_all(srv, [t for t, _ in tickets])
+    records = session_records(seed, n_sessions)
+    # positions are assigned in submission order per session
+    pos = np.zeros(n_sessions, dtype=np.int64)
+    for (tk, off), (sess, n, dist, dtype, param) in zip(tickets, reqs):
+        assert off == pos[sess]
+        per = -(-n // 64)
+        pos[sess] += (per + 1) // 2 * 2 if dist == P.MRG_NORMAL else per
+    base = pool.data_ptr()
+    for (tk, off), (sess, n, dist, dtype, param) in zip(tickets, reqs):
+        done, addr, t_done = srv.poll(tk)
+        assert done and t_done > 0
+        start = addr - base
+        got = pool[start:start + n * ESZ[dtype]].view(TDT[dtype])
+        want = alone(records, sess, off, n, dist, dtype, param)
+        torch.cuda.synchronize()
+        assert torch.equal(got, want[:n]), (sess, n, dist, dtype, off)
+        srv.release(tk)
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["released"] == len(reqs) and st["pool_in_use"] == 0
+    srv.close()
+
+
+def test_served_uniforms_match_oracle():
+    """Served f64 uniforms equal the oracle's numbers for the session's streams
+    at the assigned position."""
+    seed = workloads.random_seed(56)
+    pool = torch.empty(8 << 20, dtype=torch.uint8, device="cuda")
+    srv = P.Server(3, seed, pool)
+    reqs = [(0, 1000), (1, 64 * 7 + 3), (0, 5000), (2, 1), (0, 129)]
+    tks = [srv.submit(s, n, P.MRG_UNIFORM, P.MRG_F64) for s, n in reqs]
+    wait_all(srv, [t for t, _ in tks])
+    oc = np.array(seed, dtype=np.uint32)
+    rec = O.create_streams(O.MRG32K3A, oc, 3 * 64)
+    for (tk, off), (sess, n) in zip(tks, reqs):
+        done, addr, _ = srv.poll(tk)
+        start = addr - pool.data_ptr()
+        got = pool[start:start + 8 * n].view(torch.float64).cpu().numpy()
+        r = rec[sess * 64:(sess + 1) * 64].copy()
+        O.advance(O.MRG32K3A, r, off)
+        want = O.generate(O.MRG32K3A, r, n)
+        assert np.array_equal(got, want)
+        srv.release(tk)
+    srv.close()
+
+
+def test_admission_waits_for_memory():
+    """A pool that holds only a few outputs: requests are admitted as earlier
+    ones are released, in order, and every one completes."""
+    seed = workloads.random_seed(57)
+    pool = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")  # 1 MiB
+    srv = P.Server(4, seed, pool, lanes=2, max_batch=8)
+    n = 40000  # 320 KB of f64: three fit
+    tks = [srv.submit(i % 4, n)[0] for i in range(20)]
+    assert srv.submit_status(0, (1 << 20) // 8 + 64) == -5  # larger than the pool: refused
+    done_order = []
+    t0 = time.time()
+    while len(done_order) < len(tks):
+        for tk in tks:
+            if tk in done_order:
+                continue
+            d, _, _ = srv.poll(tk)
+            if d:
+                done_order.append(tk)
+                srv.release(tk)
+        assert time.time() - t0 < 60
+        time.sleep(0.0005)
+    st = srv.stats()
+    assert st["pool_peak"] <= (1 << 20) and st["rejected"] == 1
+    assert st["completed"] == 20
+    srv.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_drive_open_loop(mode):
+    seed = workloads.random_seed(58)
+    pool = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    srv = P.Server(256, seed, pool, mode=mode)
+    t, sess, lens = workloads.poisson_arrivals(2000.0, 0.25, rng_seed=3)
+    lat, span = srv.drive((t * 1e9).astype(np.uint64), sess, lens)
+    assert len(lat) == len(t) and np.all(lat > 0)
+    assert span > 0
+    st = srv.stats()
+    assert st["completed"] == len(t) and st["pool_in_use"] == 0
+    srv.close()
