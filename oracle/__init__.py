@@ -42,6 +42,7 @@ def lib():
             L = ctypes.CDLL(_LIB_PATH)
             u32p = ctypes.POINTER(ctypes.c_uint32)
             u64p = ctypes.POINTER(ctypes.c_uint64)
+            i32p = ctypes.POINTER(ctypes.c_int32)
             vp = ctypes.c_void_p
             c_int, c_u64, c_dbl = ctypes.c_int, ctypes.c_uint64, ctypes.c_double
             sig = {
@@ -65,6 +66,13 @@ def lib():
                 "orc_generate_range": (c_int, [c_int, u32p, c_u64, c_u64, c_int, c_int, c_dbl, vp,
                                                c_u64, c_u64]),
                 "orc_generate": (c_int, [c_int, u32p, c_u64, c_u64, c_int, c_int, c_dbl, vp]),
+                "orc_hyper_invert": (c_int, [c_dbl, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]),
+                "orc_table_sample_ld": (c_int, [c_int, u32p, c_int, c_int, i32p, i32p, i32p, c_int]),
+                "orc_table_stat_ld": (c_dbl, [c_int, c_int, i32p, c_int]),
+                "orc_tables": (c_int, [c_int, u32p, c_u64, i32p, i32p, i32p, i32p, i32p,
+                                       ctypes.POINTER(c_dbl)]),
+                "orc_fisher_count": (c_u64, [c_int, u32p, c_u64, c_int, c_int, i32p,
+                                             ctypes.POINTER(c_dbl)]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(L, name)
@@ -212,3 +220,53 @@ def generate(gen, streams, n, dist=UNIFORM, dtype=F64, param=1.0, threads=1):
         t.join()
     assert all(rc == 0 for rc in rcs)
     return out
+
+
+# ------------------------------------------------------------- Fisher tables
+def _i32p(a):
+    assert a.dtype == np.int32 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def hyper_invert(u, Np, K, n):
+    return int(lib().orc_hyper_invert(u, Np, K, n))
+
+
+def table_sample(gen, state, rows, cols):
+    """One table with the given margins from a 6-word state (advanced)."""
+    r = np.ascontiguousarray(rows, dtype=np.int32)
+    c = np.ascontiguousarray(cols, dtype=np.int32)
+    tab = np.zeros((len(r), len(c)), dtype=np.int32)
+    rc = lib().orc_table_sample_ld(gen, _u32p(state), len(r), len(c), _i32p(r), _i32p(c), _i32p(tab), len(c))
+    assert rc == 0
+    return tab
+
+
+def table_stat(tab):
+    t = np.ascontiguousarray(tab, dtype=np.int32)
+    return float(lib().orc_table_stat_ld(t.shape[0], t.shape[1], _i32p(t), t.shape[1]))
+
+
+def tables(gen, streams, I, J, rows, cols, stats=True):
+    """Tables t from streams t (records advanced in place): int32 [n,5,5] and
+    float64 statistics [n]."""
+    n = streams.shape[0]
+    out = np.zeros((n, 5, 5), dtype=np.int32)
+    st = np.zeros(n, dtype=np.float64)
+    rc = lib().orc_tables(gen, _u32p(streams), n, _i32p(np.ascontiguousarray(I, dtype=np.int32)),
+                          _i32p(np.ascontiguousarray(J, dtype=np.int32)),
+                          _i32p(np.ascontiguousarray(rows, dtype=np.int32)),
+                          _i32p(np.ascontiguousarray(cols, dtype=np.int32)), _i32p(out),
+                          st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if stats else None)
+    assert rc == 0
+    return out, st
+
+
+def fisher_count(gen, streams, observed):
+    """(count of replicates with statistic <= observed, observed statistic);
+    replicate b uses stream b (records advanced in place)."""
+    obs = np.ascontiguousarray(observed, dtype=np.int32)
+    o = ctypes.c_double()
+    cnt = lib().orc_fisher_count(gen, _u32p(streams), streams.shape[0], obs.shape[0], obs.shape[1],
+                                 _i32p(obs), ctypes.byref(o))
+    return int(cnt), o.value

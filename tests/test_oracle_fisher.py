@@ -1,0 +1,130 @@
+"""Pins of the oracle's contingency-table sampler (Section 4) to facts
+outside itself: the paper's printed thresholds, exact hypergeometric
+quantiles, exact enumeration of small tables, and the paper's p-value."""
+import itertools
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads
+from conftest import read_golden
+
+GEN = O.MRG32K3A
+
+
+def _golden_table(name):
+    return np.array([[int(v) for v in r] for r in read_golden(name)], dtype=np.int32)
+
+
+def _golden_meta(name, key):
+    from conftest import GOLDEN
+    import os
+    for line in open(os.path.join(GOLDEN, name)):
+        if line.startswith(f"# {key}:"):
+            return line.split(":", 1)[1].split()
+
+
+@pytest.mark.parametrize("name", ["fisher_month.txt", "fisher_week.txt"])
+def test_paper_thresholds(name):
+    """Section 4.1 / 4.2: the printed threshold is -sum log(n_ij!) of the
+    printed table (Tables 1 and 2), to every printed digit."""
+    tab = _golden_table(name)
+    val, dec = _golden_meta(name, "threshold")
+    assert abs(O.table_stat(tab) - float(val)) <= 0.5 * 10.0 ** (-int(dec))
+
+
+def _hyper_cdf(Np, K, n):
+    lo, hi = max(0, n - (Np - K)), min(n, K)
+    tot = math.comb(Np, n)
+    cdf, acc = [], Fraction(0)
+    for x in range(lo, hi + 1):
+        acc += Fraction(math.comb(K, x) * math.comb(Np - K, n - x), tot)
+        cdf.append((x, acc))
+    return cdf
+
+
+@pytest.mark.parametrize("Np,K,n", [(10, 4, 3), (30, 12, 17), (200, 5, 150), (400, 180, 200),
+                                    (57, 57, 20), (57, 0, 20), (12, 7, 12), (1000, 300, 400)])
+def test_inversion_is_the_hypergeometric_quantile(Np, K, n):
+    """The entry sampled from u is the smallest x with u <= F(x), F the exact
+    hypergeometric cdf (rational arithmetic), away from the cdf's jumps."""
+    cdf = _hyper_cdf(Np, K, n)
+    rnd = np.random.default_rng(Np * 7 + K)
+    us = list(rnd.uniform(0, 1, size=400)) + [1e-300, 0.5, 1 - 1e-12]
+    for u in us:
+        want = next(x for x, F in cdf if Fraction(u) <= F)
+        if any(abs(float(F) - u) < 1e-9 for _, F in cdf):
+            continue
+        assert O.hyper_invert(float(u), Np, K, n) == want, (u, Np, K, n)
+
+
+def test_tables_keep_margins_and_consume_cells():
+    I, J, rows, cols = workloads.contingency_margins(300, rng_seed=4)
+    seed = workloads.random_seed(6)
+    rec = O.create_streams(GEN, seed.copy(), 300)
+    work = rec.copy()
+    tabs, stats = O.tables(GEN, work, I, J, rows, cols)
+    for t in range(300):
+        tb = tabs[t, :I[t], :J[t]]
+        assert np.all(tb >= 0)
+        np.testing.assert_array_equal(tb.sum(axis=1), rows[t, :I[t]])
+        np.testing.assert_array_equal(tb.sum(axis=0), cols[t, :J[t]])
+        assert np.all(tabs[t, I[t]:, :] == 0) and np.all(tabs[t, :, J[t]:] == 0)
+        # exactly (I-1)(J-1) uniforms were drawn
+        s = rec[t, :6].copy()
+        O.jump(GEN, s, int((I[t] - 1) * (J[t] - 1)))
+        np.testing.assert_array_equal(work[t, :6], s)
+        assert stats[t] == O.table_stat(tb)
+
+
+def _enumerate(rows, cols):
+    """All tables with the margins, with their exact probabilities under the
+    null (multivariate hypergeometric): prod r! prod c! / (N! prod n!)."""
+    I, J = len(rows), len(cols)
+    N = sum(rows)
+    out = []
+    for cells in itertools.product(*[range(min(r, c) + 1) for r in rows[:-1] for c in cols[:-1]]):
+        t = np.zeros((I, J), dtype=np.int64)
+        t[:-1, :-1] = np.array(cells).reshape(I - 1, J - 1)
+        t[:-1, -1] = np.array(rows[:-1]) - t[:-1, :-1].sum(axis=1)
+        t[-1, :] = np.array(cols) - t[:-1, :].sum(axis=0)
+        if (t < 0).any() or t[-1].sum() != rows[-1]:
+            continue
+        num = math.prod(math.factorial(r) for r in rows) * math.prod(math.factorial(c) for c in cols)
+        den = math.factorial(N) * math.prod(math.factorial(int(v)) for v in t.flat)
+        out.append((tuple(t.flat), Fraction(num, den)))
+    return out
+
+
+@pytest.mark.parametrize("rows,cols", [([3, 4], [2, 5]), ([3, 2, 4], [4, 2, 3]), ([5, 6], [3, 4, 4])])
+def test_table_distribution_matches_exact_enumeration(rows, cols):
+    """Sequential sampling by inversion gives Fisher's null distribution:
+    chi-square against the exact table probabilities (20000 tables)."""
+    probs = _enumerate(rows, cols)
+    assert sum(p for _, p in probs) == 1
+    B = 20000
+    rec = O.create_streams(GEN, workloads.random_seed(11), B)
+    counts = {}
+    for b in range(B):
+        t = O.table_sample(GEN, rec[b, :6].copy(), rows, cols)
+        counts[tuple(t.flat)] = counts.get(tuple(t.flat), 0) + 1
+    keys = {k for k, _ in probs}
+    assert set(counts) <= keys
+    chi2 = sum((counts.get(k, 0) - B * float(p)) ** 2 / (B * float(p)) for k, p in probs)
+    dof = len(probs) - 1
+    assert chi2 < dof + 6 * math.sqrt(2 * dof) + 10, (chi2, dof)
+
+
+def test_month_pvalue_near_paper():
+    """Section 4.1 reports p = 0.403 (and 0.404 from stats::fisher.test) for
+    Table 1; 4000 oracle replicates must agree within 4 standard errors."""
+    tab = _golden_table("fisher_month.txt")
+    B = 4000
+    rec = O.create_streams(GEN, workloads.random_seed(12), B)
+    cnt, obs = O.fisher_count(GEN, rec, tab)
+    p = (1 + cnt) / (B + 1)
+    se = math.sqrt(0.403 * 0.597 / B)
+    assert abs(p - 0.403) < 4 * se, p
