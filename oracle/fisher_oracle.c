@@ -25,6 +25,7 @@
  * u * W <= w(lo) + ... + w(x), W = w(lo) + ... + w(hi), sums taken in order.
  * Built with -ffp-contract=off.
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
@@ -125,7 +126,11 @@ int orc_tables(int gen, uint32_t* streams, uint64_t n, const int32_t* I, const i
 
 /* Section 4: B replicates of the observed I x J table (row-major, stride J),
  * replicate b from stream b.  Returns the number of replicates whose
- * statistic is at most the observed one; *observed_stat receives that. */
+ * statistic is at most the observed one; *observed_stat receives that.
+ * Reading: "at most" with R's near-tie rule, statistic <= observed /
+ * (1 + 64 eps), so that tables whose statistic equals the observed one
+ * mathematically count whatever the last bit of their rounded sums (Section 4
+ * compares with stats::fisher.test, which counts this way). */
 uint64_t orc_fisher_count(int gen, uint32_t* streams, uint64_t B, int I, int J, const int32_t* observed,
                           double* observed_stat) {
     int32_t r[FT_DIM] = {0}, c[FT_DIM] = {0}, tab[FT_DIM * FT_DIM];
@@ -136,10 +141,11 @@ uint64_t orc_fisher_count(int gen, uint32_t* streams, uint64_t B, int I, int J, 
         }
     double o = orc_table_stat_ld(I, J, observed, J);
     if (observed_stat) *observed_stat = o;
+    const double threshold = o / (1.0 + 64.0 * DBL_EPSILON);
     uint64_t count = 0;
     for (uint64_t b = 0; b < B; ++b) {
         orc_table_sample_ld(gen, streams + b * 18, I, J, r, c, tab, J);
-        if (orc_table_stat_ld(I, J, tab, J) <= o) ++count;
+        if (orc_table_stat_ld(I, J, tab, J) <= threshold) ++count;
     }
     return count;
 }
