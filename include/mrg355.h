@@ -186,6 +186,43 @@ mrg_status mrg_streams_import(mrg_generator gen, const void* host_buf, size_t le
                               size_t n, size_t* n_out, mrg_creator* creator, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * The Monte-Carlo Fisher test of Section 4: random contingency tables with
+ * fixed margins, one stream per table.  Entries are drawn row by row in
+ * row-major order, each by inversion of its hypergeometric distribution given
+ * the entries before it, with one uniform of the table's stream: entry (i,j)
+ * is the smallest x in [lo, hi] with u*W <= w(lo)+...+w(x), where w(lo) = 1,
+ * w(x+1) = w(x)*((K-x)(n-x))/((x+1)(N'-K-n+x+1)) in double precision, n the
+ * row's remaining total, K column j's remaining total, N' the units left in
+ * columns j.. of rows i..; the last entry of each row and the last row are
+ * determined.  A table uses (I-1)(J-1) steps of its stream, which advances.
+ * The statistic of a table is -sum log(n_ij!), summed row-major.
+ * ------------------------------------------------------------------------ */
+
+/* n tables: table t has shape I[t] x J[t] (1..5 each), row totals
+ * rows[5t..5t+I-1], column totals cols[5t..5t+J-1] (all device int32), and
+ * uses stream t of `dev_streams`.  Writes tables[25t..25t+24] (5 x 5,
+ * row-major, zero padded) and stats[t] (optional, may be NULL).  A table with
+ * a shape out of range, a negative margin, unequal row and column sums or a
+ * grand total above 2^20 gets zeros and a NaN statistic and does not advance
+ * its stream. */
+mrg_status mrg_tables_sample(mrg_generator gen, mrg_stream* dev_streams, size_t n, const int32_t* dev_I,
+                             const int32_t* dev_J, const int32_t* dev_rows, const int32_t* dev_cols,
+                             int32_t* dev_tables, double* dev_stats, hipStream_t stream);
+
+/* fisher.sim (Section 4): B replicates of the margins of `observed` (host,
+ * I x J row-major, 1 <= I, J <= 32, non-negative, grand total <= 2^20),
+ * replicate b from stream b.  *dev_count (device) receives the number of
+ * replicates whose statistic is <= observed / (1 + 64 eps) (ties counted as
+ * stats::fisher.test does); stats (device, B entries, optional) the
+ * replicates' statistics; *observed_stat (host, optional) the observed one.
+ * The p-value is (1 + count) / (B + 1) (mrg_fisher_pvalue).  Asynchronous;
+ * no memset, so it may be captured in a graph. */
+mrg_status mrg_fisher_sim(mrg_generator gen, mrg_stream* dev_streams, uint64_t B, int I, int J,
+                          const int32_t* observed, uint64_t* dev_count, double* dev_stats,
+                          double* observed_stat, hipStream_t stream);
+double     mrg_fisher_pvalue(uint64_t count, uint64_t B);
+
+/* ------------------------------------------------------------------------
  * Batching: many generation requests of uneven lengths, each on its own
  * streams, in one persistent launch (graph-capturable).  Every request gives
  * exactly the numbers and final states that mrg_generate would give for it.

@@ -118,6 +118,10 @@ def lib():
             "mrg_batch_request_times": (i32, [vp, vp, ctypes.POINTER(ctypes.c_uint64), vp]),
             "mrg_batch_autotune": (i32, [vp, vp, sz, vp, ctypes.POINTER(mrg_batch_cfg),
                                          ctypes.POINTER(ctypes.c_double)]),
+            "mrg_tables_sample": (i32, [i32, vp, sz, vp, vp, vp, vp, vp, vp, vp]),
+            "mrg_fisher_sim": (i32, [i32, vp, u64, i32, i32, ctypes.POINTER(ctypes.c_int32), vp, vp,
+                                     ctypes.POINTER(ctypes.c_double), vp]),
+            "mrg_fisher_pvalue": (ctypes.c_double, [u64, u64]),
             "mrg_now_ns": (u64, []),
             "mrg_server_create": (i32, [ctypes.POINTER(mrg_server_cfg), ctypes.POINTER(vp)]),
             "mrg_server_destroy": (None, [vp]),
@@ -142,6 +146,7 @@ EXPORTED = ["mrg_abi_version", "mrg_status_string", "mrg_last_error", "mrg_seed_
             "mrg_creator_init", "mrg_streams_create_host", "mrg_streams_create_device",
             "mrg_streams_reset", "mrg_streams_advance", "mrg_generate", "mrg_generate_ex",
             "mrg_streams_export_size", "mrg_streams_export", "mrg_streams_import",
+            "mrg_tables_sample", "mrg_fisher_sim", "mrg_fisher_pvalue",
             "mrg_batch_plan_create", "mrg_batch_plan_destroy", "mrg_batch_workspace_size",
             "mrg_batch_tile_count", "mrg_batch_upload", "mrg_batch_launch",
             "mrg_batch_request_times", "mrg_batch_autotune", "mrg_now_ns", "mrg_server_create",
@@ -292,6 +297,61 @@ def mrg_streams_import(data, out, creator=None, gen=MRG_GEN_MRG32K3A, stream=Non
                                     ctypes.byref(creator) if creator is not None else None,
                                     _stream(stream)))
     return cnt.value
+
+
+def mrg_tables_sample(streams, I, J, rows, cols, tables=None, stats=None, n=None,
+                      gen=MRG_GEN_MRG32K3A, stream=None):
+    """Random contingency tables with fixed margins (Section 4): table t of
+    shape I[t] x J[t] (<= 5 x 5) with margins rows[t, :5], cols[t, :5] (device
+    int32) from stream t.  Returns (tables [n, 5, 5] int32, stats [n] f64 or
+    None); pass stats=True to have the statistics allocated."""
+    import torch
+    n = I.shape[0] if n is None else n
+    if n > streams.shape[0] or n > I.shape[0] or n > J.shape[0]:
+        raise ValueError("n exceeds the streams or shapes given")
+    if rows.numel() < 5 * n or cols.numel() < 5 * n:
+        raise ValueError("rows and cols need 5 entries per table")
+    for t in (I, J, rows, cols):
+        if t.dtype != torch.int32 or not t.is_contiguous():
+            raise ValueError("shapes and margins must be contiguous int32 tensors")
+    if tables is not None and tables.numel() < 25 * n:
+        raise ValueError("tables needs 25 entries per table")
+    if tables is None:
+        tables = torch.empty((max(n, 1), 5, 5), dtype=torch.int32, device=streams.device)
+    if stats is True:
+        stats = torch.empty(max(n, 1), dtype=torch.float64, device=streams.device)
+    _check(lib().mrg_tables_sample(gen, _dptr(streams), n, _dptr(I), _dptr(J), _dptr(rows), _dptr(cols),
+                                   _dptr(tables), _dptr(stats) if stats is not None else None,
+                                   _stream(stream)))
+    return tables, stats
+
+
+def mrg_fisher_sim(streams, observed, B=None, stats=None, count=None, gen=MRG_GEN_MRG32K3A, stream=None):
+    """Monte-Carlo Fisher test (Section 4) of the host table `observed` with B
+    replicates, replicate b from stream b.  Returns (count device tensor
+    [1] int64, observed statistic, stats tensor or None).  Pass stats=True to
+    keep the replicates' statistics."""
+    import torch
+    obs = np.ascontiguousarray(np.asarray(observed, dtype=np.int32))
+    if obs.ndim != 2:
+        raise ValueError("observed must be a 2-D table")
+    B = streams.shape[0] if B is None else B
+    if B > streams.shape[0]:
+        raise ValueError("B exceeds the number of streams")
+    if count is None:
+        count = torch.empty(1, dtype=torch.int64, device=streams.device)
+    if stats is True:
+        stats = torch.empty(max(B, 1), dtype=torch.float64, device=streams.device)
+    ostat = ctypes.c_double()
+    _check(lib().mrg_fisher_sim(gen, _dptr(streams), B, obs.shape[0], obs.shape[1],
+                                obs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dptr(count),
+                                _dptr(stats) if stats is not None else None, ctypes.byref(ostat),
+                                _stream(stream)))
+    return count, ostat.value, stats
+
+
+def mrg_fisher_pvalue(count, B):
+    return lib().mrg_fisher_pvalue(int(count), int(B))
 
 
 def as_u32(t):

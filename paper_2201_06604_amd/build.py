@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmrg355.so")
-SOURCES = ["mrg_kernels.hip", "mrg_api.cpp", "mrg_batch.cpp", "mrg_server.cpp"]
+SOURCES = ["mrg_kernels.hip", "mrg_tables.hip", "mrg_api.cpp", "mrg_batch.cpp", "mrg_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

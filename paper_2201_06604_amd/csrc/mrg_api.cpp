@@ -5,6 +5,7 @@
 // unchanged.  Device work goes to the caller's hipStream_t.
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -218,6 +219,62 @@ mrg_status mrg_generate(mrg_generator gen, mrg_stream* dev, size_t n_streams, ui
                         mrg_dist dist, mrg_dtype dtype, double param, void* dev_out,
                         hipStream_t stream) {
     return mrg_generate_ex(gen, dev, n_streams, n, dist, dtype, param, dev_out, nullptr, stream);
+}
+
+mrg_status mrg_tables_sample(mrg_generator gen, mrg_stream* dev_streams, size_t n, const int32_t* dev_I,
+                             const int32_t* dev_J, const int32_t* dev_rows, const int32_t* dev_cols,
+                             int32_t* dev_tables, double* dev_stats, hipStream_t stream) {
+    if (mrg_status st = check_gen(gen)) return st;
+    if (n == 0) return ok();
+    if (!dev_streams || !dev_I || !dev_J || !dev_rows || !dev_cols || !dev_tables)
+        return fail(MRG_E_INVALID_ARG, "NULL pointer");
+    if (n > (static_cast<size_t>(1) << 31)) return fail(MRG_E_INVALID_ARG, "n above 2^31");
+    if (reinterpret_cast<uintptr_t>(dev_streams) % 4 || reinterpret_cast<uintptr_t>(dev_tables) % 4 ||
+        reinterpret_cast<uintptr_t>(dev_I) % 4 || reinterpret_cast<uintptr_t>(dev_J) % 4 ||
+        reinterpret_cast<uintptr_t>(dev_rows) % 4 || reinterpret_cast<uintptr_t>(dev_cols) % 4 ||
+        reinterpret_cast<uintptr_t>(dev_stats) % 8)
+        return fail(MRG_E_INVALID_ARG, "misaligned pointer");
+    hipError_t e = launch_tables(reinterpret_cast<uint32_t*>(dev_streams), n, dev_I, dev_J, dev_rows, dev_cols,
+                                 dev_tables, dev_stats, stream);
+    if (e != hipSuccess) return hip_fail(e, "tables launch");
+    return ok();
+}
+
+mrg_status mrg_fisher_sim(mrg_generator gen, mrg_stream* dev_streams, uint64_t B, int I, int J,
+                          const int32_t* observed, uint64_t* dev_count, double* dev_stats,
+                          double* observed_stat, hipStream_t stream) {
+    if (mrg_status st = check_gen(gen)) return st;
+    if (!observed || !dev_count) return fail(MRG_E_INVALID_ARG, "NULL observed table or count");
+    if (I < 1 || J < 1 || I > kFisherMaxDim || J > kFisherMaxDim)
+        return fail(MRG_E_INVALID_ARG, "table shape must be 1..%d x 1..%d", kFisherMaxDim, kFisherMaxDim);
+    if (B && !dev_streams) return fail(MRG_E_INVALID_ARG, "NULL streams");
+    if (B > (static_cast<uint64_t>(1) << 31)) return fail(MRG_E_INVALID_ARG, "B above 2^31");
+    if (reinterpret_cast<uintptr_t>(dev_count) % 8 || reinterpret_cast<uintptr_t>(dev_stats) % 8 ||
+        reinterpret_cast<uintptr_t>(dev_streams) % 4)
+        return fail(MRG_E_INVALID_ARG, "misaligned pointer");
+    int32_t r[kFisherMaxDim] = {0}, c[kFisherMaxDim] = {0};
+    int64_t total = 0;
+    double stat = 0.0;  // -sum log(n!), row-major, with the host's lgamma
+    for (int i = 0; i < I; ++i)
+        for (int j = 0; j < J; ++j) {
+            const int32_t v = observed[i * J + j];
+            if (v < 0) return fail(MRG_E_INVALID_ARG, "negative entry in the observed table");
+            r[i] += v;
+            c[j] += v;
+            total += v;
+            stat -= std::lgamma(static_cast<double>(v) + 1.0);
+        }
+    if (total > kTableMaxTotal) return fail(MRG_E_INVALID_ARG, "grand total above 2^20");
+    const double threshold = stat / (1.0 + 64.0 * DBL_EPSILON);
+    hipError_t e = launch_fisher(reinterpret_cast<uint32_t*>(dev_streams), B, I, J, r, c, threshold,
+                                 reinterpret_cast<unsigned long long*>(dev_count), dev_stats, stream);
+    if (e != hipSuccess) return hip_fail(e, "fisher launch");
+    if (observed_stat) *observed_stat = stat;
+    return ok();
+}
+
+double mrg_fisher_pvalue(uint64_t count, uint64_t B) {
+    return (1.0 + static_cast<double>(count)) / (static_cast<double>(B) + 1.0);
 }
 
 mrg_status mrg_streams_export_size(size_t n, int with_creator, size_t* bytes) {

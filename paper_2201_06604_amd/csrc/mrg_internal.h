@@ -113,6 +113,14 @@ hipError_t launch_create(uint32_t* out, uint64_t n, const uint32_t creator[6], h
 hipError_t launch_reset(uint32_t* streams, uint64_t n, int kind, hipStream_t s);
 hipError_t launch_advance(uint32_t* streams, uint64_t n, uint64_t steps, hipStream_t s);
 
+// Contingency tables (Section 4).
+constexpr int kFisherMaxDim = 32;
+constexpr int64_t kTableMaxTotal = 1 << 20;  // grand total of one table at most
+hipError_t launch_tables(uint32_t* streams, uint64_t n, const int32_t* I, const int32_t* J, const int32_t* rows,
+                         const int32_t* cols, int32_t* tabs, double* stats, hipStream_t s);
+hipError_t launch_fisher(uint32_t* streams, uint64_t B, int I, int J, const int32_t* r, const int32_t* c,
+                         double threshold, unsigned long long* count, double* stats, hipStream_t s);
+
 // Host-side jump math (same tables the device uses).
 void host_jump_pow2(uint32_t state[6], uint64_t k, bool stream_tables);  // A^(k [*2^127]) state
 

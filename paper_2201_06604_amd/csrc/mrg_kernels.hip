@@ -25,6 +25,7 @@
 
 #include <type_traits>
 
+#include "mrg_engine.h"
 #include "mrg_internal.h"
 #include "mrg_math.h"
 
@@ -44,132 +45,6 @@ __device__ __forceinline__ void dev_jump(uint32_t x[6], uint64_t e) {
     for (int b = 0; e; ++b, e >>= 1)
         if (e & 1) dev_apply(g_tab.step_pow2[0][b], g_tab.step_pow2[1][b], x);
 }
-
-// -------------------------------------------------------- integer engine
-// p < 2^54 -> p mod m1.  p = h*2^32 + l with h < 2^22; 2^32 = 209 (mod m1).
-__device__ __forceinline__ uint32_t fold_m1(uint64_t p) {
-    uint32_t h = static_cast<uint32_t>(p >> 32), l = static_cast<uint32_t>(p);
-    uint64_t t = static_cast<uint64_t>(__umul24(h, kC1)) + l;          // < 2^32 + 2^30
-    uint32_t r = static_cast<uint32_t>(t) + static_cast<uint32_t>(t >> 32) * kC1;
-    return min(r, r - kM1);                                             // r < 2^32 < 2 m1
-}
-
-// p < 2^54 -> p mod m2.  h < 2^21, 2^32 = 22853 (mod m2).
-__device__ __forceinline__ uint32_t fold_m2(uint64_t p) {
-    uint32_t h = static_cast<uint32_t>(p >> 32), l = static_cast<uint32_t>(p);
-    uint64_t t = static_cast<uint64_t>(h) * kC2 + l;                   // < 2^36 + 2^32
-    uint32_t h2 = static_cast<uint32_t>(t >> 32), l2 = static_cast<uint32_t>(t);
-    uint64_t t2 = static_cast<uint64_t>(__umul24(h2, kC2)) + l2;       // < 2^32 + 2^19
-    uint32_t r = static_cast<uint32_t>(t2) + static_cast<uint32_t>(t2 >> 32) * kC2;
-    return min(r, r - kM2);
-}
-
-struct IntEngine {
-    uint32_t a0, a1, a2, b0, b1, b2;  // (x1[n-3], x1[n-2], x1[n-1]), (x2[...])
-
-    __device__ __forceinline__ void load(const uint32_t x[6]) {
-        a0 = x[0]; a1 = x[1]; a2 = x[2]; b0 = x[3]; b1 = x[4]; b2 = x[5];
-    }
-    __device__ __forceinline__ void save(uint32_t x[6]) const {
-        x[0] = a0; x[1] = a1; x[2] = a2; x[3] = b0; x[4] = b1; x[5] = b2;
-    }
-    // New x1 from (x1[n-2], x1[n-3]) replaces x1[n-3]; new x2 from (x2[n-1],
-    // x2[n-3]) replaces x2[n-3]; returns z in [1, m1].
-    static __device__ __forceinline__ uint32_t kernel(uint32_t& o1, uint32_t m2_1, uint32_t& o2,
-                                                      uint32_t n1_2) {
-        uint64_t p1 = static_cast<uint64_t>(kA12) * m2_1 + static_cast<uint64_t>(kA13N) * (kM1 - o1);
-        uint64_t p2 = static_cast<uint64_t>(kA21) * n1_2 + static_cast<uint64_t>(kA23N) * (kM2 - o2);
-        uint32_t x1 = fold_m1(p1), x2 = fold_m2(p2);
-        o1 = x1;
-        o2 = x2;
-        return x1 > x2 ? x1 - x2 : x1 - x2 + kM1;
-    }
-    // Phase-P step of a 3-step cycle: the ring of registers rotates by naming,
-    // so no moves are needed.
-    template <int P>
-    __device__ __forceinline__ uint32_t step() {
-        if (P == 0) return kernel(a0, a1, b0, b2);
-        if (P == 1) return kernel(a1, a2, b1, b0);
-        return kernel(a2, a0, b2, b1);
-    }
-    __device__ __forceinline__ uint32_t step_rot() {
-        uint32_t z = kernel(a0, a1, b0, b2);
-        uint32_t t = a0; a0 = a1; a1 = a2; a2 = t;
-        t = b0; b0 = b1; b1 = b2; b2 = t;
-        return z;
-    }
-};
-
-// ------------------------------------------------------------ fp64 engine
-constexpr double kM1d = static_cast<double>(kM1);
-constexpr double kM2d = static_cast<double>(kM2);
-constexpr double kInvM1 = 1.0 / kM1d;
-constexpr double kInvM2 = 1.0 / kM2d;
-
-// p an integer with |p| < 2^53 -> an integer r = p (mod m) with
-// |r| <= m/2 + 4, exactly: q is the nearest quotient (off by at most one),
-// and p - q*m is exact in one FMA.
-__device__ __forceinline__ double f64_rem(double p, double m, double inv_m) {
-    double q = __builtin_rint(p * inv_m);
-    return __builtin_fma(-q, m, p);
-}
-
-// |r| <= m/2 + 4 -> r mod m in [0, m): floor(r/m) is -1 or 0.
-__device__ __forceinline__ double f64_canon(double r, double m, double inv_m) {
-    double t = __builtin_floor(r * inv_m);
-    return __builtin_fma(-t, m, r);
-}
-
-// Component 1 is carried as any residue with |x| <= m1/2 + 4 (its value only
-// matters mod m1); component 2 is kept in [0, m2) because z uses its value.
-// Products stay below 2^53 in magnitude either way, so every FMA is exact.
-struct F64Engine {
-    double a0, a1, a2, b0, b1, b2;
-
-    __device__ __forceinline__ void load(const uint32_t x[6]) {
-        a0 = x[0]; a1 = x[1]; a2 = x[2]; b0 = x[3]; b1 = x[4]; b2 = x[5];
-    }
-    __device__ __forceinline__ void save(uint32_t x[6]) const {
-        x[0] = static_cast<uint32_t>(f64_canon(a0, kM1d, kInvM1));
-        x[1] = static_cast<uint32_t>(f64_canon(a1, kM1d, kInvM1));
-        x[2] = static_cast<uint32_t>(f64_canon(a2, kM1d, kInvM1));
-        x[3] = static_cast<uint32_t>(b0); x[4] = static_cast<uint32_t>(b1);
-        x[5] = static_cast<uint32_t>(b2);
-    }
-    static __device__ __forceinline__ double kernel(double& o1, double m2_1, double& o2, double n1_2) {
-        double p1 = __builtin_fma(static_cast<double>(kA12), m2_1, -(static_cast<double>(kA13N) * o1));
-        double p2 = __builtin_fma(static_cast<double>(kA21), n1_2, -(static_cast<double>(kA23N) * o2));
-        double x1 = f64_rem(p1, kM1d, kInvM1);
-        double x2 = f64_canon(f64_rem(p2, kM2d, kInvM2), kM2d, kInvM2);
-        o1 = x1;
-        o2 = x2;
-        // z = d mod m1 in [1, m1], d = x1 - x2 in [-(1.5 m1 + 4), m1/2 + 4]:
-        // t = floor((d-1)/m1) in {-2, -1, 0}.  Near a multiple of m1 the
-        // quotient differs from it by at least 1/m1, far above the rounding
-        // of the FMA, so t is exact.
-        double d = x1 - x2;
-        double t = __builtin_floor(__builtin_fma(d, kInvM1, -kInvM1));
-        return __builtin_fma(-t, kM1d, d);
-    }
-    template <int P>
-    __device__ __forceinline__ double step() {
-        if (P == 0) return kernel(a0, a1, b0, b2);
-        if (P == 1) return kernel(a1, a2, b1, b0);
-        return kernel(a2, a0, b2, b1);
-    }
-    __device__ __forceinline__ double step_rot() {
-        double z = kernel(a0, a1, b0, b2);
-        double t = a0; a0 = a1; a1 = a2; a2 = t;
-        t = b0; b0 = b1; b1 = b2; b2 = t;
-        return z;
-    }
-};
-
-// ------------------------------------------------------------- transforms
-__device__ __forceinline__ double to_f64(uint32_t z) { return static_cast<double>(z); }
-__device__ __forceinline__ double to_f64(double z) { return z; }
-__device__ __forceinline__ uint32_t to_u32(uint32_t z) { return z; }
-__device__ __forceinline__ uint32_t to_u32(double z) { return static_cast<uint32_t>(z); }
 
 // Largest float <= u for u in [2^-126, 1): drop the low 29 mantissa bits
 // after rebasing the exponent (1023 -> 127).

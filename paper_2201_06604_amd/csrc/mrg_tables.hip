@@ -1,0 +1,194 @@
+// mrg_tables.hip -- the Monte-Carlo Fisher test consumer of the streams
+// (Section 4): random contingency tables with fixed margins, one stream per
+// table, entries drawn in row-major order by inversion of their conditional
+// hypergeometric distributions, one uniform per free entry.
+//
+// Inversion (identical operations to the definition used for parity): entry
+// (i, j) given the entries before it takes x in [lo, hi] with weights
+// w(lo) = 1, w(x+1) = w(x) * ((K-x)(n-x)) / ((x+1)(N'-K-n+x+1)) in double
+// precision (exact integer products, one rounded multiply, one rounded
+// divide); the entry is the smallest x with u*W <= w(lo)+...+w(x), sums in
+// order.  No FMA contraction (the library is built with -ffp-contract=off),
+// so the integers match bit for bit.
+//
+// One lane owns one table.  The loops' trip counts depend on the margins, so
+// lanes of a wave diverge; that is the price of exact inversion.
+#include <hip/hip_runtime.h>
+
+#include "mrg_engine.h"
+#include "mrg_internal.h"
+#include "mrg_math.h"
+
+namespace mrg355 {
+
+__device__ __forceinline__ int hyper_invert(double u, int64_t Np, int64_t K, int64_t n) {
+    int64_t lo = n - (Np - K);
+    if (lo < 0) lo = 0;
+    const int64_t hi = n < K ? n : K;
+    if (hi <= lo) return static_cast<int>(lo);
+    double W = 0.0, w = 1.0;
+    for (int64_t x = lo; x <= hi; ++x) {
+        W += w;
+        if (x < hi) {
+            const double num = static_cast<double>((K - x) * (n - x));
+            const double den = static_cast<double>((x + 1) * (Np - K - n + x + 1));
+            w = w * num / den;
+        }
+    }
+    const double target = u * W;
+    double s = 0.0;
+    w = 1.0;
+    for (int64_t x = lo; x <= hi; ++x) {
+        s += w;
+        if (target <= s) return static_cast<int>(x);
+        const double num = static_cast<double>((K - x) * (n - x));
+        const double den = static_cast<double>((x + 1) * (Np - K - n + x + 1));
+        w = w * num / den;
+    }
+    return static_cast<int>(hi);
+}
+
+__device__ __forceinline__ double log_factorial(int n) { return lgamma(static_cast<double>(n) + 1.0); }
+
+// One I x J table (I, J <= MAXD) with row totals r[], column totals c[]:
+// entries to tab[i*ld + j] (when tab is not null); returns -sum log(n_ij!)
+// summed row-major.  The engine advances (I-1)(J-1) steps.
+template <int MAXD, typename Engine>
+__device__ double sample_table(Engine& e, int I, int J, const int32_t* r, const int32_t* c, int32_t* tab, int ld) {
+    int32_t crem[MAXD];
+    for (int j = 0; j < J; ++j) crem[j] = c[j];
+    double stat = 0.0;
+    for (int i = 0; i < I - 1; ++i) {
+        int64_t rrem = r[i];
+        int64_t Np = 0;  // units left in columns j..J-1 over rows i..I-1
+        for (int j = 0; j < J; ++j) Np += crem[j];
+        for (int j = 0; j < J - 1; ++j) {
+            const double u = to_f64(e.step_rot()) * kNorm;
+            const int x = hyper_invert(u, Np, crem[j], rrem);
+            if (tab) tab[i * ld + j] = x;
+            stat -= log_factorial(x);
+            rrem -= x;
+            Np -= crem[j];
+            crem[j] -= x;
+        }
+        if (tab) tab[i * ld + J - 1] = static_cast<int32_t>(rrem);  // determined by the row total
+        stat -= log_factorial(static_cast<int>(rrem));
+        crem[J - 1] -= static_cast<int32_t>(rrem);
+    }
+    for (int j = 0; j < J; ++j) {  // the last row is what the columns have left
+        if (tab) tab[(I - 1) * ld + j] = crem[j];
+        stat -= log_factorial(crem[j]);
+    }
+    return stat;
+}
+
+// Tables t < n: shape I[t] x J[t] (<= 5 x 5), margins rows[t][5], cols[t][5],
+// from stream t; outputs tabs[t][5][5] (zero padded) and stats[t] (optional).
+// A table whose shape is out of range or whose margins are negative, differ
+// in total or total more than kTableMaxTotal gets zeros and a NaN statistic,
+// and its stream is left as it was (the checks also bound every loop).
+__global__ void __launch_bounds__(256) tables_kernel(uint32_t* streams, uint64_t n, const int32_t* I,
+                                                     const int32_t* J, const int32_t* rows, const int32_t* cols,
+                                                     int32_t* tabs, double* stats) {
+    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int32_t* out = tabs + t * 25;
+#pragma unroll
+    for (int k = 0; k < 25; ++k) out[k] = 0;
+    const int It = I[t], Jt = J[t];
+    bool ok = It >= 1 && It <= 5 && Jt >= 1 && Jt <= 5;
+    int64_t rs = 0, cs = 0;
+    for (int k = 0; ok && k < It; ++k) {
+        ok = rows[t * 5 + k] >= 0;
+        rs += rows[t * 5 + k];
+    }
+    for (int k = 0; ok && k < Jt; ++k) {
+        ok = cols[t * 5 + k] >= 0;
+        cs += cols[t * 5 + k];
+    }
+    ok = ok && rs == cs && rs <= kTableMaxTotal;
+    if (!ok) {
+        if (stats) stats[t] = __builtin_nan("");
+        return;
+    }
+    uint32_t* rec = streams + t * 18;
+    uint32_t x[6];
+#pragma unroll
+    for (int w = 0; w < 6; ++w) x[w] = rec[w];
+    F64Engine e;
+    e.load(x);
+    const double stat = sample_table<5>(e, It, Jt, rows + t * 5, cols + t * 5, out, 5);
+    if (stats) stats[t] = stat;
+    e.save(x);
+#pragma unroll
+    for (int w = 0; w < 6; ++w) rec[w] = x[w];
+}
+
+// The count is cleared by a kernel, not a memset, so the launch can be
+// captured in a graph.
+__global__ void fisher_clear_kernel(unsigned long long* count) { *count = 0; }
+
+struct FisherArgs {
+    uint32_t* streams;
+    uint64_t B;
+    int I, J;
+    int32_t r[kFisherMaxDim], c[kFisherMaxDim];
+    double threshold;      // observed statistic / (1 + 64 eps)
+    unsigned long long* count;
+    double* stats;
+};
+
+// Replicate b < B of the observed table's margins from stream b; counts the
+// replicates whose statistic is <= threshold (one atomic per wave; every
+// lane executes it, with the wave's count on lane 0 and 0 elsewhere).
+__global__ void __launch_bounds__(256) fisher_kernel(FisherArgs a) {
+    const uint64_t b = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63;
+    bool hit = false;
+    if (b < a.B) {
+        uint32_t* rec = a.streams + b * 18;
+        uint32_t x[6];
+#pragma unroll
+        for (int w = 0; w < 6; ++w) x[w] = rec[w];
+        F64Engine e;
+        e.load(x);
+        const double stat = sample_table<kFisherMaxDim>(e, a.I, a.J, a.r, a.c, nullptr, 0);
+        hit = stat <= a.threshold;
+        if (a.stats) a.stats[b] = stat;
+        e.save(x);
+#pragma unroll
+        for (int w = 0; w < 6; ++w) rec[w] = x[w];
+    }
+    const unsigned long long wave_hits = __popcll(__ballot(hit));
+    atomicAdd(a.count, lane == 0 ? wave_hits : 0ull);
+}
+
+hipError_t launch_tables(uint32_t* streams, uint64_t n, const int32_t* I, const int32_t* J, const int32_t* rows,
+                         const int32_t* cols, int32_t* tabs, double* stats, hipStream_t s) {
+    hipLaunchKernelGGL(tables_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, streams, n,
+                       I, J, rows, cols, tabs, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_fisher(uint32_t* streams, uint64_t B, int I, int J, const int32_t* r, const int32_t* c,
+                         double threshold, unsigned long long* count, double* stats, hipStream_t s) {
+    FisherArgs a{};
+    a.streams = streams;
+    a.B = B;
+    a.I = I;
+    a.J = J;
+    for (int k = 0; k < kFisherMaxDim; ++k) {
+        a.r[k] = k < I ? r[k] : 0;
+        a.c[k] = k < J ? c[k] : 0;
+    }
+    a.threshold = threshold;
+    a.count = count;
+    a.stats = stats;
+    hipLaunchKernelGGL(fisher_clear_kernel, dim3(1), dim3(1), 0, s, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || B == 0) return e;
+    hipLaunchKernelGGL(fisher_kernel, dim3(static_cast<unsigned>((B + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace mrg355

@@ -263,3 +263,33 @@ def test_server_create_validation():
                 dict(mode=2), dict(lanes=65), dict(sps=70000)]:
         assert L.mrg_server_create(ctypes.byref(cfg(**bad)), ctypes.byref(srv)) == -1, bad
     assert L.mrg_server_create(ctypes.byref(cfg(seed=[0, 0, 0, 1, 1, 1])), ctypes.byref(srv)) == -2
+
+
+def _fisher_status(obs, B=10, dev_count=64, dev_streams=4096):
+    obs = np.ascontiguousarray(np.asarray(obs, dtype=np.int32))
+    return P.lib().mrg_fisher_sim(P.MRG_GEN_MRG32K3A, ctypes.c_void_p(dev_streams), B, obs.shape[0],
+                                  obs.shape[1], obs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  ctypes.c_void_p(dev_count), None, None, None)
+
+
+def test_fisher_sim_validation():
+    """Shape, entries, total, pointers and B are checked before any launch."""
+    assert _fisher_status(np.ones((33, 2))) == -1
+    assert _fisher_status(np.ones((2, 33))) == -1
+    assert _fisher_status([[1, -1], [2, 3]]) == -1
+    assert _fisher_status([[1 << 19, 1 << 19], [1, 0]]) == -1  # total above 2^20
+    assert _fisher_status([[1, 2], [3, 4]], dev_count=0) == -1
+    assert _fisher_status([[1, 2], [3, 4]], dev_count=12) == -1  # misaligned count
+    assert _fisher_status([[1, 2], [3, 4]], dev_streams=0) == -1
+    assert _fisher_status([[1, 2], [3, 4]], B=(1 << 31) + 1) == -1
+    assert P.mrg_fisher_pvalue(0, 999) == pytest.approx(1e-3)
+
+
+def test_tables_sample_validation():
+    L = P.lib()
+    v = ctypes.c_void_p(4096)
+    assert L.mrg_tables_sample(P.MRG_GEN_MRG32K3A, v, 0, None, None, None, None, None, None, None) == 0
+    assert L.mrg_tables_sample(P.MRG_GEN_MRG32K3A, v, 5, v, None, v, v, v, None, None) == -1
+    assert L.mrg_tables_sample(P.MRG_GEN_MRG32K3A, v, 5, v, v, v, v, ctypes.c_void_p(4098), None, None) == -1
+    assert L.mrg_tables_sample(P.MRG_GEN_MRG32K3A, v, 5, v, v, v, v, v, ctypes.c_void_p(4100), None) == -1
+    assert L.mrg_tables_sample(9, v, 5, v, v, v, v, v, None, None) == -1

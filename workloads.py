@@ -67,25 +67,29 @@ def contingency_margins(n_tables: int, rng_seed: int = DEFAULT_RNG_SEED,
                         dim_lo: int = 2, dim_hi: int = 5, tot_lo: int = 5, tot_hi: int = 200):
     """Random table shapes I x J (uniform in [dim_lo, dim_hi]) and margins:
     row totals uniform in [tot_lo, tot_hi]; column totals uniform in the same
-    range for the first J-1 columns, the last one making the sums equal,
-    all column totals redrawn until it too lies in [tot_lo, tot_hi].
-    Returns (I, J, rows[n,5], cols[n,5]) with zero padding."""
+    range for the first J-1 columns, the last one making the sums equal; a
+    table whose last column total falls outside [tot_lo, tot_hi] has all its
+    totals redrawn.  Returns (I, J, rows[n,5], cols[n,5]) with zero padding."""
     rng = np.random.default_rng(rng_seed)
     I = rng.integers(dim_lo, dim_hi + 1, size=n_tables)
     J = rng.integers(dim_lo, dim_hi + 1, size=n_tables)
-    rows = np.zeros((n_tables, 5), dtype=np.int32)
-    cols = np.zeros((n_tables, 5), dtype=np.int32)
-    for t in range(n_tables):
-        while True:
-            r = rng.integers(tot_lo, tot_hi + 1, size=I[t])
-            c = rng.integers(tot_lo, tot_hi + 1, size=J[t] - 1)
-            last = int(r.sum()) - int(c.sum())
-            if tot_lo <= last <= tot_hi:
-                break
-        rows[t, :I[t]] = r
-        cols[t, :J[t] - 1] = c
-        cols[t, J[t] - 1] = last
-    return I.astype(np.int32), J.astype(np.int32), rows, cols
+    rows = np.zeros((n_tables, 5), dtype=np.int64)
+    cols = np.zeros((n_tables, 5), dtype=np.int64)
+    k = np.arange(5)
+    todo = np.arange(n_tables)
+    while todo.size:
+        r = rng.integers(tot_lo, tot_hi + 1, size=(todo.size, 5))
+        c = rng.integers(tot_lo, tot_hi + 1, size=(todo.size, 5))
+        r[k[None, :] >= I[todo, None]] = 0
+        c[k[None, :] >= J[todo, None] - 1] = 0
+        last = r.sum(axis=1) - c.sum(axis=1)
+        ok = (last >= tot_lo) & (last <= tot_hi)
+        sel = todo[ok]
+        rows[sel] = r[ok]
+        c[ok.nonzero()[0], J[sel] - 1] = last[ok]
+        cols[sel] = c[ok]
+        todo = todo[~ok]
+    return I.astype(np.int32), J.astype(np.int32), rows.astype(np.int32), cols.astype(np.int32)
 
 
 def poisson_arrivals(rate_per_s: float, duration_s: float, n_sessions: int = 256,
