@@ -42,16 +42,20 @@ mrg_status hip_fail(hipError_t e, const char* what) {
 }
 
 mrg_status check_gen(mrg_generator gen) {
-    if (gen == MRG_GEN_MRG32K3A) return MRG_OK;
-    if (gen == MRG_GEN_MRG31K3P) return fail(MRG_E_UNSUPPORTED, "generator MRG31k3p is not built");
+    if (gen == MRG_GEN_MRG32K3A || gen == MRG_GEN_MRG31K3P) return MRG_OK;
     return fail(MRG_E_INVALID_ARG, "unknown generator id %d", static_cast<int>(gen));
 }
 
+// The library's generator id (kGen32k3a / kGen31k3p) of a checked ABI id.
+int gid(mrg_generator gen) { return gen == MRG_GEN_MRG32K3A ? kGen32k3a : kGen31k3p; }
+
 // The seed / state validity rule: words 0-2 below m1, 3-5 below m2, neither
-// triple all zero.
-bool state_valid(const uint32_t s[6]) {
-    if (s[0] >= kM1 || s[1] >= kM1 || s[2] >= kM1) return false;
-    if (s[3] >= kM2 || s[4] >= kM2 || s[5] >= kM2) return false;
+// triple all zero (the moduli of the generator).
+bool state_valid(mrg_generator gen, const uint32_t s[6]) {
+    const uint32_t m1 = gen == MRG_GEN_MRG32K3A ? kM1 : kP1;
+    const uint32_t m2 = gen == MRG_GEN_MRG32K3A ? kM2 : kP2;
+    if (s[0] >= m1 || s[1] >= m1 || s[2] >= m1) return false;
+    if (s[3] >= m2 || s[4] >= m2 || s[5] >= m2) return false;
     if ((s[0] | s[1] | s[2]) == 0) return false;
     if ((s[3] | s[4] | s[5]) == 0) return false;
     return true;
@@ -88,7 +92,7 @@ const char* mrg_last_error(void) { return g_err.c_str(); }
 mrg_status mrg_seed_check(mrg_generator gen, const uint32_t seed[6]) {
     if (mrg_status st = check_gen(gen)) return st;
     if (!seed) return fail(MRG_E_INVALID_ARG, "seed is NULL");
-    if (!state_valid(seed))
+    if (!state_valid(gen, seed))
         return fail(MRG_E_INVALID_SEED,
                     "seed words 0-2 must be < m1, words 3-5 < m2, and neither triple all zero");
     return ok();
@@ -105,17 +109,17 @@ mrg_status mrg_streams_create_host(mrg_generator gen, mrg_creator* creator, size
                                    mrg_stream* host_out) {
     if (mrg_status st = check_gen(gen)) return st;
     if (!creator) return fail(MRG_E_INVALID_ARG, "creator is NULL");
-    if (!state_valid(creator->s)) return fail(MRG_E_INVALID_SEED, "creator holds an invalid state");
+    if (!state_valid(gen, creator->s)) return fail(MRG_E_INVALID_SEED, "creator holds an invalid state");
     if (n == 0) return ok();
     if (!host_out) return fail(MRG_E_INVALID_ARG, "host_out is NULL");
-    // J = A^(2^127): one matrix-vector product per stream.
+    // J = A^Z: one matrix-vector product per stream.
     uint32_t x[6];
     std::memcpy(x, creator->s, sizeof(x));
     for (size_t i = 0; i < n; ++i) {
         std::memcpy(host_out[i].cur, x, sizeof(x));
         std::memcpy(host_out[i].start, x, sizeof(x));
         std::memcpy(host_out[i].sub, x, sizeof(x));
-        host_jump_pow2(x, 1, true);
+        host_jump_pow2(gid(gen), x, 1, true);
     }
     std::memcpy(creator->s, x, sizeof(x));
     return ok();
@@ -125,15 +129,15 @@ mrg_status mrg_streams_create_device(mrg_generator gen, mrg_creator* creator, si
                                      mrg_stream* dev_out, hipStream_t stream) {
     if (mrg_status st = check_gen(gen)) return st;
     if (!creator) return fail(MRG_E_INVALID_ARG, "creator is NULL");
-    if (!state_valid(creator->s)) return fail(MRG_E_INVALID_SEED, "creator holds an invalid state");
+    if (!state_valid(gen, creator->s)) return fail(MRG_E_INVALID_SEED, "creator holds an invalid state");
     if (n == 0) return ok();
     if (!dev_out) return fail(MRG_E_INVALID_ARG, "dev_out is NULL");
     if (reinterpret_cast<uintptr_t>(dev_out) % 4) return fail(MRG_E_INVALID_ARG, "dev_out misaligned");
     if (n > (static_cast<size_t>(1) << 40)) return fail(MRG_E_INVALID_ARG, "n too large");
     uint32_t next[6];
     std::memcpy(next, creator->s, sizeof(next));
-    host_jump_pow2(next, static_cast<uint64_t>(n), true);
-    hipError_t e = launch_create(reinterpret_cast<uint32_t*>(dev_out), n, creator->s, stream);
+    host_jump_pow2(gid(gen), next, static_cast<uint64_t>(n), true);
+    hipError_t e = launch_create(gid(gen), reinterpret_cast<uint32_t*>(dev_out), n, creator->s, stream);
     if (e != hipSuccess) return hip_fail(e, "create_kernel launch");
     std::memcpy(creator->s, next, sizeof(next));
     return ok();
@@ -147,7 +151,7 @@ mrg_status mrg_streams_reset(mrg_generator gen, mrg_stream* dev, size_t n, mrg_r
     if (n == 0) return ok();
     if (!dev) return fail(MRG_E_INVALID_ARG, "dev is NULL");
     if (reinterpret_cast<uintptr_t>(dev) % 4) return fail(MRG_E_INVALID_ARG, "dev misaligned");
-    hipError_t e = launch_reset(reinterpret_cast<uint32_t*>(dev), n, static_cast<int>(kind), stream);
+    hipError_t e = launch_reset(gid(gen), reinterpret_cast<uint32_t*>(dev), n, static_cast<int>(kind), stream);
     if (e != hipSuccess) return hip_fail(e, "reset_kernel launch");
     return ok();
 }
@@ -158,7 +162,7 @@ mrg_status mrg_streams_advance(mrg_generator gen, mrg_stream* dev, size_t n, uin
     if (n == 0 || steps == 0) return ok();
     if (!dev) return fail(MRG_E_INVALID_ARG, "dev is NULL");
     if (reinterpret_cast<uintptr_t>(dev) % 4) return fail(MRG_E_INVALID_ARG, "dev misaligned");
-    hipError_t e = launch_advance(reinterpret_cast<uint32_t*>(dev), n, steps, stream);
+    hipError_t e = launch_advance(gid(gen), reinterpret_cast<uint32_t*>(dev), n, steps, stream);
     if (e != hipSuccess) return hip_fail(e, "advance_kernel launch");
     return ok();
 }
@@ -209,6 +213,7 @@ mrg_status mrg_generate_ex(mrg_generator gen, mrg_stream* dev, size_t n_streams,
     L.dist = static_cast<int>(dist);
     L.dtype = static_cast<int>(dtype);
     L.param = dist == MRG_EXPONENTIAL ? 1.0 / param : 1.0;
+    if (gen == MRG_GEN_MRG31K3P) L.arith = kArith31;  // its own engine; cfg->arith applies to MRG32k3a
     plan_generate(L);
     hipError_t e = launch_generate(L, stream);
     if (e != hipSuccess) return hip_fail(e, "generate launch");
@@ -234,7 +239,7 @@ mrg_status mrg_tables_sample(mrg_generator gen, mrg_stream* dev_streams, size_t 
         reinterpret_cast<uintptr_t>(dev_rows) % 4 || reinterpret_cast<uintptr_t>(dev_cols) % 4 ||
         reinterpret_cast<uintptr_t>(dev_stats) % 8)
         return fail(MRG_E_INVALID_ARG, "misaligned pointer");
-    hipError_t e = launch_tables(reinterpret_cast<uint32_t*>(dev_streams), n, dev_I, dev_J, dev_rows, dev_cols,
+    hipError_t e = launch_tables(gid(gen), reinterpret_cast<uint32_t*>(dev_streams), n, dev_I, dev_J, dev_rows, dev_cols,
                                  dev_tables, dev_stats, stream);
     if (e != hipSuccess) return hip_fail(e, "tables launch");
     return ok();
@@ -266,7 +271,7 @@ mrg_status mrg_fisher_sim(mrg_generator gen, mrg_stream* dev_streams, uint64_t B
         }
     if (total > kTableMaxTotal) return fail(MRG_E_INVALID_ARG, "grand total above 2^20");
     const double threshold = stat / (1.0 + 64.0 * DBL_EPSILON);
-    hipError_t e = launch_fisher(reinterpret_cast<uint32_t*>(dev_streams), B, I, J, r, c, threshold,
+    hipError_t e = launch_fisher(gid(gen), reinterpret_cast<uint32_t*>(dev_streams), B, I, J, r, c, threshold,
                                  reinterpret_cast<unsigned long long*>(dev_count), dev_stats, stream);
     if (e != hipSuccess) return hip_fail(e, "fisher launch");
     if (observed_stat) *observed_stat = stat;
@@ -335,14 +340,14 @@ mrg_status mrg_streams_import(mrg_generator gen, const void* host_buf, size_t le
     uint32_t tmp[6];
     for (uint64_t i = 0; i < cnt * 3; ++i) {  // cur, start and sub of every record
         std::memcpy(tmp, p + kHeaderBytes + i * 24, 24);
-        if (!state_valid(tmp))
+        if (!state_valid(gen, tmp))
             return fail(MRG_E_CORRUPT_STATE, "record %llu holds an invalid state",
                         static_cast<unsigned long long>(i / 3));
     }
     uint32_t cre[6] = {0, 0, 0, 0, 0, 0};
     if (flags) {
         std::memcpy(cre, p + kHeaderBytes + cnt * kRecordBytes, 24);
-        if (!state_valid(cre)) return fail(MRG_E_CORRUPT_STATE, "saved creator is invalid");
+        if (!state_valid(gen, cre)) return fail(MRG_E_CORRUPT_STATE, "saved creator is invalid");
     }
     if (cnt > n) return fail(MRG_E_NOMEM, "buffer holds %llu streams, room for %zu",
                              static_cast<unsigned long long>(cnt), n);

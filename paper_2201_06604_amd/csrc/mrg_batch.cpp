@@ -286,7 +286,8 @@ extern "C" {
 
 mrg_status mrg_batch_plan_create(mrg_generator gen, const mrg_request* reqs, size_t n_req,
                                  const mrg_batch_cfg* cfg, mrg_batch_plan** plan) {
-    if (gen == MRG_GEN_MRG31K3P) return mrg355_fail(MRG_E_UNSUPPORTED, "generator MRG31k3p is not built");
+    if (gen == MRG_GEN_MRG31K3P)
+        return mrg355_fail(MRG_E_UNSUPPORTED, "batched launches run MRG32k3a streams only");
     if (gen != MRG_GEN_MRG32K3A) return mrg355_fail(MRG_E_INVALID_ARG, "unknown generator id");
     if (!plan) return mrg355_fail(MRG_E_INVALID_ARG, "plan is NULL");
     if (n_req && !reqs) return mrg355_fail(MRG_E_INVALID_ARG, "reqs is NULL");

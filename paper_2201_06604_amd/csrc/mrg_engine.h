@@ -1,10 +1,18 @@
-// mrg_engine.h -- the exact MRG32k3a step on gfx950, in two interchangeable
-// arithmetic forms (device code, included by the kernel sources).
+// mrg_engine.h -- the exact generator steps on gfx950 (device code, included
+// by the kernel sources).  MRG32k3a in two interchangeable arithmetic forms:
 //
 //   IntEngine  32x32->64 multiply-adds, reduced with 2^32 = c (mod 2^32 - c)
 //   F64Engine  the same integers held exactly in fp64: every product is below
 //              2^53 and each remainder p - q*m is one exact FMA
-// Both give identical integers z in [1, m1].
+//
+// Both give identical integers z in [1, m1].  MRG31k3p (Engine31) uses 32-bit
+// rotations for its power-of-two multipliers modulo the Mersenne prime p1 and
+// one 64-bit fold modulo p2.
+//
+// Every engine keeps each component as a ring of three registers holding
+// (x[n-3], x[n-2], x[n-1]); a step overwrites x[n-3] with x[n], so a 3-step
+// cycle needs no register moves.  Both recurrences read x1[n-2], x1[n-3],
+// x2[n-1] and x2[n-3], so the ring logic is shared.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -54,6 +62,61 @@ struct IntEngine {
     }
     // Phase-P step of a 3-step cycle: the ring of registers rotates by naming,
     // so no moves are needed.
+    template <int P>
+    __device__ __forceinline__ uint32_t step() {
+        if (P == 0) return kernel(a0, a1, b0, b2);
+        if (P == 1) return kernel(a1, a2, b1, b0);
+        return kernel(a2, a0, b2, b1);
+    }
+    __device__ __forceinline__ uint32_t step_rot() {
+        uint32_t z = kernel(a0, a1, b0, b2);
+        uint32_t t = a0; a0 = a1; a1 = a2; a2 = t;
+        t = b0; b0 = b1; b1 = b2; b2 = t;
+        return z;
+    }
+};
+
+// ------------------------------------------------------- MRG31k3p engine
+// 2^k x mod (2^31 - 1) for x < 2^31 - 1: a 31-bit rotation (2^31 = 1).  The
+// result is below 2^31 - 1 because x is.
+template <int K>
+__device__ __forceinline__ uint32_t rot31(uint32_t x) {
+    return ((x << K) & kP1) | (x >> (31 - K));
+}
+
+// a + b mod m for a, b < m < 2^31: one conditional subtraction (min picks the
+// reduced value; a + b - m wraps above it when a + b < m).
+__device__ __forceinline__ uint32_t add_mod31(uint32_t a, uint32_t b, uint32_t m) {
+    const uint32_t s = a + b;
+    return min(s, s - m);
+}
+
+struct Engine31 {
+    uint32_t a0, a1, a2, b0, b1, b2;  // (x1[n-3], x1[n-2], x1[n-1]), (x2[...])
+
+    // The stored state is newest-first: (x1[n-1], x1[n-2], x1[n-3], x2[...]).
+    __device__ __forceinline__ void load(const uint32_t x[6]) {
+        a0 = x[2]; a1 = x[1]; a2 = x[0]; b0 = x[5]; b1 = x[4]; b2 = x[3];
+    }
+    __device__ __forceinline__ void save(uint32_t x[6]) const {
+        x[0] = a2; x[1] = a1; x[2] = a0; x[3] = b2; x[4] = b1; x[5] = b0;
+    }
+    // o1 = x1[n-3] (becomes x1[n]), m2_1 = x1[n-2], o2 = x2[n-3] (becomes
+    // x2[n]), n1_2 = x2[n-1]; returns z in [1, p1].
+    static __device__ __forceinline__ uint32_t kernel(uint32_t& o1, uint32_t m2_1, uint32_t& o2,
+                                                      uint32_t n1_2) {
+        // x1[n] = 2^22 x1[n-2] + 2^7 x1[n-3] + x1[n-3]  (mod p1)
+        const uint32_t x1 = add_mod31(add_mod31(rot31<22>(m2_1), rot31<7>(o1), kP1), o1, kP1);
+        // x2[n] = 2^15 (x2[n-1] + x2[n-3]) + x2[n-3]  (mod p2), p < 2^47 + 2^31
+        const uint64_t p = (static_cast<uint64_t>(n1_2 + o2) << 15) + o2;
+        const uint32_t h = static_cast<uint32_t>(p >> 31), l = static_cast<uint32_t>(p) & 0x7fffffffu;
+        const uint32_t t = __umul24(h, kQ2) + l;                      // h < 2^17: t < 2^32
+        const uint32_t t2 = (t >> 31) * kQ2 + (t & 0x7fffffffu);      // < 2^31 + q2 < 2 p2
+        const uint32_t x2 = min(t2, t2 - kP2);
+        o1 = x1;
+        o2 = x2;
+        return x1 > x2 ? x1 - x2 : x1 - x2 + kP1;
+    }
     template <int P>
     __device__ __forceinline__ uint32_t step() {
         if (P == 0) return kernel(a0, a1, b0, b2);

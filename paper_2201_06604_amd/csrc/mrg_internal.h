@@ -11,7 +11,8 @@ namespace mrg355 {
 
 enum Dist { kUniform = 0, kNormal = 1, kExponential = 2, kRaw = 3 };
 enum DType { kF64 = 0, kF32 = 1, kU32 = 2 };
-enum Arith { kArithAuto = 0, kArithInt = 1, kArithF64 = 2 };
+// kArith31 is the MRG31k3p engine (set by the library for that generator).
+enum Arith { kArithAuto = 0, kArithInt = 1, kArithF64 = 2, kArith31 = 3 };
 
 // One plain generation launch over S streams (see mrg_generate).
 struct GenLaunch {
@@ -109,19 +110,20 @@ int device_cu_count();
 int batch_blocks_per_cu();
 hipError_t launch_generate(const GenLaunch& L, hipStream_t s);
 
-hipError_t launch_create(uint32_t* out, uint64_t n, const uint32_t creator[6], hipStream_t s);
-hipError_t launch_reset(uint32_t* streams, uint64_t n, int kind, hipStream_t s);
-hipError_t launch_advance(uint32_t* streams, uint64_t n, uint64_t steps, hipStream_t s);
+// gen: kGen32k3a or kGen31k3p (mrg_math.h).
+hipError_t launch_create(int gen, uint32_t* out, uint64_t n, const uint32_t creator[6], hipStream_t s);
+hipError_t launch_reset(int gen, uint32_t* streams, uint64_t n, int kind, hipStream_t s);
+hipError_t launch_advance(int gen, uint32_t* streams, uint64_t n, uint64_t steps, hipStream_t s);
 
 // Contingency tables (Section 4).
 constexpr int kFisherMaxDim = 32;
 constexpr int64_t kTableMaxTotal = 1 << 20;  // grand total of one table at most
-hipError_t launch_tables(uint32_t* streams, uint64_t n, const int32_t* I, const int32_t* J, const int32_t* rows,
+hipError_t launch_tables(int gen, uint32_t* streams, uint64_t n, const int32_t* I, const int32_t* J, const int32_t* rows,
                          const int32_t* cols, int32_t* tabs, double* stats, hipStream_t s);
-hipError_t launch_fisher(uint32_t* streams, uint64_t B, int I, int J, const int32_t* r, const int32_t* c,
+hipError_t launch_fisher(int gen, uint32_t* streams, uint64_t B, int I, int J, const int32_t* r, const int32_t* c,
                          double threshold, unsigned long long* count, double* stats, hipStream_t s);
 
 // Host-side jump math (same tables the device uses).
-void host_jump_pow2(uint32_t state[6], uint64_t k, bool stream_tables);  // A^(k [*2^127]) state
+void host_jump_pow2(int gen, uint32_t state[6], uint64_t k, bool stream_tables);  // A^(k [* Z]) state
 
 }  // namespace mrg355

@@ -31,19 +31,35 @@
 
 namespace mrg355 {
 
-__constant__ JumpTables g_tab = make_jump_tables();
-static constexpr JumpTables kHostTab = make_jump_tables();
+__constant__ JumpTables g_tab = make_jump_tables<kGen32k3a>();
+__constant__ JumpTables g_tab31 = make_jump_tables<kGen31k3p>();
+static constexpr JumpTables kHostTab = make_jump_tables<kGen32k3a>();
+static constexpr JumpTables kHostTab31 = make_jump_tables<kGen31k3p>();
 
 // ------------------------------------------------------------------ jumps
+template <int G>
+__device__ __forceinline__ const JumpTables& dev_tab() {
+    if constexpr (G == kGen32k3a) return g_tab;
+    else return g_tab31;
+}
+
+// x <- (M1 x[0..2], M2 x[3..5]) modulo the generator's two moduli.
+template <int G>
 __device__ __forceinline__ void dev_apply(const Mat3& M1, const Mat3& M2, uint32_t x[6]) {
-    matvec(M1, x, kC1);
-    matvec(M2, x + 3, kC2);
+    if constexpr (G == kGen32k3a) {
+        matvec<32>(M1, x, kC1);
+        matvec<32>(M2, x + 3, kC2);
+    } else {
+        matvec<31>(M1, x, kQ1);
+        matvec<31>(M2, x + 3, kQ2);
+    }
 }
 
 // x <- A^e x, e wave-uniform.
+template <int G>
 __device__ __forceinline__ void dev_jump(uint32_t x[6], uint64_t e) {
     for (int b = 0; e; ++b, e >>= 1)
-        if (e & 1) dev_apply(g_tab.step_pow2[0][b], g_tab.step_pow2[1][b], x);
+        if (e & 1) dev_apply<G>(dev_tab<G>().step_pow2[0][b], dev_tab<G>().step_pow2[1][b], x);
 }
 
 // Largest float <= u for u in [2^-126, 1): drop the low 29 mantissa bits
@@ -59,13 +75,19 @@ template <> struct ElemOf<kF64> { using T = double; };
 template <> struct ElemOf<kF32> { using T = float; };
 template <> struct ElemOf<kU32> { using T = uint32_t; };
 
+// The scale of Section 2.2 for generator G: 1/(m1+1).
+template <int G>
+__device__ __forceinline__ constexpr double norm_of() {
+    return G == kGen32k3a ? kNorm : kNorm31;
+}
+
 // The stored value of one uniform / raw / exponential draw.
-template <int DIST, int DTYPE, typename Z>
+template <int DIST, int DTYPE, int G, typename Z>
 __device__ __forceinline__ typename ElemOf<DTYPE>::T value1(Z z, double inv_rate) {
     if constexpr (DIST == kRaw) {
         return to_u32(z);
     } else {
-        double u = to_f64(z) * kNorm;
+        double u = to_f64(z) * norm_of<G>();
         if constexpr (DIST == kExponential) {
             double v = -log(u) * inv_rate;
             if constexpr (DTYPE == kF64) return v;
@@ -78,9 +100,9 @@ __device__ __forceinline__ typename ElemOf<DTYPE>::T value1(Z z, double inv_rate
 }
 
 // Box-Muller pair (Algorithm 1) from two consecutive steps of one stream.
-template <typename Z>
+template <int G, typename Z>
 __device__ __forceinline__ void box_muller(Z z1, Z z2, double& x, double& y) {
-    double u1 = to_f64(z1) * kNorm, u2 = to_f64(z2) * kNorm;
+    double u1 = to_f64(z1) * norm_of<G>(), u2 = to_f64(z2) * norm_of<G>();
     double r = sqrt(-2.0 * log(u1));
     double s, c;
     sincospi(2.0 * u2, &s, &c);
@@ -142,7 +164,10 @@ __device__ __forceinline__ void store_1(__amdgpu_buffer_rsrc_t r, uint32_t voff,
 // draw units [by*chunk, (by+1)*chunk).  Wave-uniform arguments.
 template <int DIST, int DTYPE, int ARITH, int SPL, bool NT>
 __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uint32_t by) {
-    using Engine = typename std::conditional<ARITH == kArithF64, F64Engine, IntEngine>::type;
+    using Engine = typename std::conditional<
+        ARITH == kArith31, Engine31,
+        typename std::conditional<ARITH == kArithF64, F64Engine, IntEngine>::type>::type;
+    constexpr int G = ARITH == kArith31 ? kGen31k3p : kGen32k3a;
     using T = typename ElemOf<DTYPE>::T;
     constexpr uint32_t ESZ = sizeof(T);
     constexpr uint32_t WS = 64 * SPL;                   // streams per wave
@@ -175,7 +200,7 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
 #pragma unroll
         for (int w = 0; w < 6; ++w) x[w] = rec[w];
         const uint64_t jump = L.offset + u0 * kSpu;
-        if (jump) dev_jump(x, jump);
+        if (jump) dev_jump<G>(x, jump);
         e[i].load(x);
     }
 
@@ -210,17 +235,17 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
             pair([](Engine& g, double& x, double& y) {
                 auto z0 = g.template step<0>();
                 auto z1 = g.template step<1>();
-                box_muller(z0, z1, x, y);
+                box_muller<G>(z0, z1, x, y);
             });
             pair([](Engine& g, double& x, double& y) {
                 auto z2 = g.template step<2>();
                 auto z3 = g.template step<0>();
-                box_muller(z2, z3, x, y);
+                box_muller<G>(z2, z3, x, y);
             });
             pair([](Engine& g, double& x, double& y) {
                 auto z4 = g.template step<1>();
                 auto z5 = g.template step<2>();
-                box_muller(z4, z5, x, y);
+                box_muller<G>(z4, z5, x, y);
             });
         }
         for (; k < kend; ++k) {
@@ -230,7 +255,7 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
                 auto z0 = e[i].step_rot();
                 auto z1 = e[i].step_rot();
                 double x, y;
-                box_muller(z0, z1, x, y);
+                box_muller<G>(z0, z1, x, y);
                 px.v[i] = narrow<DTYPE>(x);
                 py.v[i] = narrow<DTYPE>(y);
             }
@@ -248,7 +273,7 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
                     auto z0 = e[i].step_rot();
                     auto z1 = e[i].step_rot();
                     double x, y;
-                    box_muller(z0, z1, x, y);
+                    box_muller<G>(z0, z1, x, y);
                     if (2 * k < cnt[i]) store_1<T, NT>(row_rsrc(row, nrec), voff + i * ESZ, narrow<DTYPE>(x));
                     if (2 * k + 1 < cnt[i])
                         store_1<T, NT>(row_rsrc(row + rowstep, nrec), voff + i * ESZ, narrow<DTYPE>(y));
@@ -261,9 +286,9 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
             Pack<T, SPL> p0, p1, p2;
 #pragma unroll
             for (int i = 0; i < SPL; ++i) {
-                p0.v[i] = value1<DIST, DTYPE>(e[i].template step<0>(), inv_rate);
-                p1.v[i] = value1<DIST, DTYPE>(e[i].template step<1>(), inv_rate);
-                p2.v[i] = value1<DIST, DTYPE>(e[i].template step<2>(), inv_rate);
+                p0.v[i] = value1<DIST, DTYPE, G>(e[i].template step<0>(), inv_rate);
+                p1.v[i] = value1<DIST, DTYPE, G>(e[i].template step<1>(), inv_rate);
+                p2.v[i] = value1<DIST, DTYPE, G>(e[i].template step<2>(), inv_rate);
             }
             store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, p0);
             row += rowstep;
@@ -275,7 +300,7 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
         for (; k < kend; ++k) {
             Pack<T, SPL> p;
 #pragma unroll
-            for (int i = 0; i < SPL; ++i) p.v[i] = value1<DIST, DTYPE>(e[i].step_rot(), inv_rate);
+            for (int i = 0; i < SPL; ++i) p.v[i] = value1<DIST, DTYPE, G>(e[i].step_rot(), inv_rate);
             store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, p);
             row += rowstep;
         }
@@ -285,7 +310,7 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
             for (int i = 0; i < SPL; ++i)
                 if (k < units[i])
                     store_1<T, NT>(row_rsrc(row, nrec), voff + i * ESZ,
-                                   value1<DIST, DTYPE>(e[i].step_rot(), inv_rate));
+                                   value1<DIST, DTYPE, G>(e[i].step_rot(), inv_rate));
             row += rowstep;
         }
     }
@@ -326,6 +351,7 @@ __global__ void __launch_bounds__(1024) gen_kernel(GenLaunch L) {
 
 // cur <- A^(steps consumed) cur for every stream, after a chunked launch:
 // cnt_s = q + (s < r) draws; normals consume 2*ceil(cnt_s/2) steps.
+template <int G>
 __global__ void __launch_bounds__(256) finalize_kernel(uint32_t* streams, uint32_t S, uint64_t q,
                                                        uint32_t r, int normal) {
     uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -337,7 +363,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(uint32_t* streams, uint32
 #pragma unroll
     for (int w = 0; w < 6; ++w) x[w] = rec[w];
     for (int b = 0; b < 64; ++b)  // uniform loop: table loads stay scalar
-        if ((steps >> b) & 1) dev_apply(g_tab.step_pow2[0][b], g_tab.step_pow2[1][b], x);
+        if ((steps >> b) & 1) dev_apply<G>(dev_tab<G>().step_pow2[0][b], dev_tab<G>().step_pow2[1][b], x);
 #pragma unroll
     for (int w = 0; w < 6; ++w) rec[w] = x[w];
 }
@@ -477,14 +503,16 @@ __global__ void __launch_bounds__(256) batch_finalize_kernel(BatchLaunch B) {
 #pragma unroll
     for (int w = 0; w < 6; ++w) x[w] = rec[w];
     for (int b = 0; b < 64; ++b)
-        if ((steps >> b) & 1) dev_apply(g_tab.step_pow2[0][b], g_tab.step_pow2[1][b], x);
+        if ((steps >> b) & 1) dev_apply<kGen32k3a>(g_tab.step_pow2[0][b], g_tab.step_pow2[1][b], x);
 #pragma unroll
     for (int w = 0; w < 6; ++w) rec[w] = x[w];
 }
 
 // ------------------------------------------------------ stream creation
-// Stream i = J^i creator with J = A^(2^127): multiply by J^(2^b) for each
-// set bit b of i (the per-bit tables are uniform scalar loads).
+// Stream i = J^i creator with J = A^Z (Z = 2^127, or 2^134 for MRG31k3p):
+// multiply by J^(2^b) for each set bit b of i (the per-bit tables are uniform
+// scalar loads).
+template <int G>
 __global__ void __launch_bounds__(256) create_kernel(uint32_t* out, uint64_t n, uint32_t c0, uint32_t c1,
                                                      uint32_t c2, uint32_t c3, uint32_t c4, uint32_t c5,
                                                      int nbits) {
@@ -492,7 +520,7 @@ __global__ void __launch_bounds__(256) create_kernel(uint32_t* out, uint64_t n, 
     if (i >= n) return;
     uint32_t x[6] = {c0, c1, c2, c3, c4, c5};
     for (int b = 0; b < nbits; ++b)
-        if ((i >> b) & 1) dev_apply(g_tab.stream_pow2[0][b], g_tab.stream_pow2[1][b], x);
+        if ((i >> b) & 1) dev_apply<G>(dev_tab<G>().stream_pow2[0][b], dev_tab<G>().stream_pow2[1][b], x);
     uint32_t* rec = out + i * 18;
 #pragma unroll
     for (int w = 0; w < 6; ++w) {
@@ -502,6 +530,7 @@ __global__ void __launch_bounds__(256) create_kernel(uint32_t* out, uint64_t n, 
     }
 }
 
+template <int G>
 __global__ void __launch_bounds__(256) reset_kernel(uint32_t* streams, uint64_t n, int kind) {
     uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -513,7 +542,7 @@ __global__ void __launch_bounds__(256) reset_kernel(uint32_t* streams, uint64_t 
     } else {
 #pragma unroll
         for (int w = 0; w < 6; ++w) x[w] = rec[12 + w];
-        if (kind == 2) dev_apply(g_tab.substream[0], g_tab.substream[1], x);
+        if (kind == 2) dev_apply<G>(dev_tab<G>().substream[0], dev_tab<G>().substream[1], x);
     }
 #pragma unroll
     for (int w = 0; w < 6; ++w) {
@@ -522,6 +551,7 @@ __global__ void __launch_bounds__(256) reset_kernel(uint32_t* streams, uint64_t 
     }
 }
 
+template <int G>
 __global__ void __launch_bounds__(256) advance_kernel(uint32_t* streams, uint64_t n, uint64_t steps) {
     uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -529,19 +559,25 @@ __global__ void __launch_bounds__(256) advance_kernel(uint32_t* streams, uint64_
     uint32_t x[6];
 #pragma unroll
     for (int w = 0; w < 6; ++w) x[w] = rec[w];
-    dev_jump(x, steps);
+    dev_jump<G>(x, steps);
 #pragma unroll
     for (int w = 0; w < 6; ++w) rec[w] = x[w];
 }
 
 // ------------------------------------------------------------ host side
-void host_jump_pow2(uint32_t state[6], uint64_t k, bool stream_tables) {
+void host_jump_pow2(int gen, uint32_t state[6], uint64_t k, bool stream_tables) {
+    const JumpTables& T = gen == kGen32k3a ? kHostTab : kHostTab31;
     for (int b = 0; k; ++b, k >>= 1) {
         if (!(k & 1)) continue;
-        const Mat3& A = stream_tables ? kHostTab.stream_pow2[0][b] : kHostTab.step_pow2[0][b];
-        const Mat3& B = stream_tables ? kHostTab.stream_pow2[1][b] : kHostTab.step_pow2[1][b];
-        matvec(A, state, kC1);
-        matvec(B, state + 3, kC2);
+        const Mat3& A = stream_tables ? T.stream_pow2[0][b] : T.step_pow2[0][b];
+        const Mat3& B = stream_tables ? T.stream_pow2[1][b] : T.step_pow2[1][b];
+        if (gen == kGen32k3a) {
+            matvec<32>(A, state, kC1);
+            matvec<32>(B, state + 3, kC2);
+        } else {
+            matvec<31>(A, state, kQ1);
+            matvec<31>(B, state + 3, kQ2);
+        }
     }
 }
 
@@ -549,21 +585,31 @@ static unsigned grid1d(uint64_t n, unsigned block) {
     return static_cast<unsigned>((n + block - 1) / block);
 }
 
-hipError_t launch_create(uint32_t* out, uint64_t n, const uint32_t c[6], hipStream_t s) {
+hipError_t launch_create(int gen, uint32_t* out, uint64_t n, const uint32_t c[6], hipStream_t s) {
     int nbits = 0;
     while (nbits < 64 && ((n - 1) >> nbits)) ++nbits;
-    hipLaunchKernelGGL(create_kernel, dim3(grid1d(n, 256)), dim3(256), 0, s, out, n, c[0], c[1], c[2],
-                       c[3], c[4], c[5], nbits);
+    if (gen == kGen32k3a)
+        hipLaunchKernelGGL(create_kernel<kGen32k3a>, dim3(grid1d(n, 256)), dim3(256), 0, s, out, n, c[0], c[1],
+                           c[2], c[3], c[4], c[5], nbits);
+    else
+        hipLaunchKernelGGL(create_kernel<kGen31k3p>, dim3(grid1d(n, 256)), dim3(256), 0, s, out, n, c[0], c[1],
+                           c[2], c[3], c[4], c[5], nbits);
     return hipGetLastError();
 }
 
-hipError_t launch_reset(uint32_t* streams, uint64_t n, int kind, hipStream_t s) {
-    hipLaunchKernelGGL(reset_kernel, dim3(grid1d(n, 256)), dim3(256), 0, s, streams, n, kind);
+hipError_t launch_reset(int gen, uint32_t* streams, uint64_t n, int kind, hipStream_t s) {
+    if (gen == kGen32k3a)
+        hipLaunchKernelGGL(reset_kernel<kGen32k3a>, dim3(grid1d(n, 256)), dim3(256), 0, s, streams, n, kind);
+    else
+        hipLaunchKernelGGL(reset_kernel<kGen31k3p>, dim3(grid1d(n, 256)), dim3(256), 0, s, streams, n, kind);
     return hipGetLastError();
 }
 
-hipError_t launch_advance(uint32_t* streams, uint64_t n, uint64_t steps, hipStream_t s) {
-    hipLaunchKernelGGL(advance_kernel, dim3(grid1d(n, 256)), dim3(256), 0, s, streams, n, steps);
+hipError_t launch_advance(int gen, uint32_t* streams, uint64_t n, uint64_t steps, hipStream_t s) {
+    if (gen == kGen32k3a)
+        hipLaunchKernelGGL(advance_kernel<kGen32k3a>, dim3(grid1d(n, 256)), dim3(256), 0, s, streams, n, steps);
+    else
+        hipLaunchKernelGGL(advance_kernel<kGen31k3p>, dim3(grid1d(n, 256)), dim3(256), 0, s, streams, n, steps);
     return hipGetLastError();
 }
 
@@ -579,7 +625,7 @@ hipError_t launch_advance(uint32_t* streams, uint64_t n, uint64_t steps, hipStre
 void plan_generate(GenLaunch& L) {
     const int esz = L.dtype == kF64 ? 8 : 4;
     const bool plain = L.dist == kUniform || L.dist == kRaw;
-    const bool cfg_given = L.block || L.chunk || L.spl || L.arith;
+    const bool cfg_given = L.block || L.chunk || L.spl || (L.arith && L.arith != kArith31);
     if (!L.arith) L.arith = kArithF64;
     if (!L.spl) L.spl = plain ? 16 / esz : 1;
     if (!L.block) L.block = (plain && esz == 4) ? 512 : 256;
@@ -644,6 +690,7 @@ static hipError_t launch_spl(const GenLaunch& L, hipStream_t s) {
 
 template <int DIST, int DTYPE>
 static hipError_t launch_dd(const GenLaunch& L, hipStream_t s) {
+    if (L.arith == kArith31) return launch_spl<DIST, DTYPE, kArith31>(L, s);
     if (L.arith == kArithF64) return launch_spl<DIST, DTYPE, kArithF64>(L, s);
     return launch_spl<DIST, DTYPE, kArithInt>(L, s);
 }
@@ -709,8 +756,12 @@ hipError_t launch_generate(const GenLaunch& L, hipStream_t s) {
     if (L.n_chunks == 0) return hipSuccess;
     hipError_t e = launch_gen_only(L, s);
     if (e != hipSuccess || L.n_chunks == 1 || L.no_writeback) return e;
-    hipLaunchKernelGGL(finalize_kernel, dim3(grid1d(L.S, 256)), dim3(256), 0, s, L.streams, L.S, L.q,
-                       L.r, L.dist == kNormal ? 1 : 0);
+    if (L.arith == kArith31)
+        hipLaunchKernelGGL(finalize_kernel<kGen31k3p>, dim3(grid1d(L.S, 256)), dim3(256), 0, s, L.streams, L.S,
+                           L.q, L.r, L.dist == kNormal ? 1 : 0);
+    else
+        hipLaunchKernelGGL(finalize_kernel<kGen32k3a>, dim3(grid1d(L.S, 256)), dim3(256), 0, s, L.streams, L.S,
+                           L.q, L.r, L.dist == kNormal ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
-// mrg_math.h -- MRG32k3a constants and exact modular matrix arithmetic for the
-// product library (host code and compile-time device tables).
+// mrg_math.h -- constants of the two generators and exact modular matrix
+// arithmetic for the product library (host code and compile-time device
+// tables).
 //
 // The generator is MRG32k3a (L'Ecuyer 1999; named by the clrng paper in
 // Sections 1, 2 and 6):
@@ -11,9 +12,19 @@
 // spacing for MRG32k3a).  Jump-ahead multiplies the per-component state
 // vector (x[n-3], x[n-2], x[n-1]) by a power of the one-step matrix.
 //
-// Reduction uses the special form m = 2^32 - c: 2^32 = c (mod m), so a 64-bit
-// value h*2^32 + l folds to h*c + l.  Everything here is constexpr so that the
-// device jump tables are computed by the compiler.
+// The second generator is MRG31k3p (L'Ecuyer and Touzin 2000), the one the
+// clrng paper itself uses (Section 2):
+//   x1[n] = (2^22 x1[n-2] + (2^7 + 1) x1[n-3]) mod p1,   p1 = 2^31 - 1
+//   x2[n] = (2^15 x2[n-1] + (2^15 + 1) x2[n-3]) mod p2,  p2 = 2^31 - 21069
+//   z[n]  = (x1[n] - x2[n]) mod p1 in [1, p1], u = z / 2^31
+// with streams 2^134 apart (Section 2.1) and substreams 2^72 apart.  Its
+// states are kept newest-first, (x[n-1], x[n-2], x[n-3]) per component, the
+// order of the stream table printed in Section 2.1, so its matrices act on
+// that order.
+//
+// Reduction uses the special form m = 2^B - c (B = 32 or 31): 2^B = c (mod m),
+// so a 64-bit value h*2^B + l folds to h*c + l.  Everything here is constexpr
+// so that the device jump tables are computed by the compiler.
 #pragma once
 
 #include <stdint.h>
@@ -42,73 +53,103 @@ constexpr double kNorm = 1.0 / 4294967088.0;
 constexpr int kStreamLog2 = 127;
 constexpr int kSubstreamLog2 = 76;
 
+constexpr uint32_t kQ1 = 1u;
+constexpr uint32_t kQ2 = 21069u;
+constexpr uint32_t kP1 = 0x80000000u - kQ1;  // 2147483647
+constexpr uint32_t kP2 = 0x80000000u - kQ2;  // 2147462579
+constexpr uint32_t kB12 = 1u << 22;          // multiplies x1[n-2]
+constexpr uint32_t kB13 = (1u << 7) + 1u;    // multiplies x1[n-3]
+constexpr uint32_t kB21 = 1u << 15;          // multiplies x2[n-1]
+constexpr uint32_t kB23 = (1u << 15) + 1u;   // multiplies x2[n-3]
+constexpr double kNorm31 = 1.0 / 2147483648.0;  // 2^-31, exact
+constexpr int kStreamLog2_31 = 134;
+constexpr int kSubstreamLog2_31 = 72;
+
+// Generator ids used inside the library (the ABI's ids minus one).
+enum Generator { kGen32k3a = 0, kGen31k3p = 1 };
+
 struct Mat3 {
     uint32_t a[9];
 };
 
-// x mod (2^32 - c) for any 64-bit x, 1 <= c < 2^15.
+// x mod (2^B - c) for any 64-bit x, B = 32 or 31, 1 <= c < 2^15.  Each fold
+// maps h*2^B + l to h*c + l; four folds bring any 64-bit value below
+// 2^B + 2c, and one conditional subtraction finishes.
+template <int B = 32>
 MRG_HD constexpr uint32_t fold64(uint64_t x, uint32_t c) {
-    x = (x >> 32) * c + (x & 0xffffffffull);  // < 2^47 + 2^32
-    x = (x >> 32) * c + (x & 0xffffffffull);  // < 2^32 + 2^30 + c
-    x = (x >> 32) * c + (x & 0xffffffffull);  // < 2^32
-    uint32_t r = static_cast<uint32_t>(x);
-    uint32_t m = 0u - c;
-    return r >= m ? r - m : r;
+    constexpr uint64_t mask = (static_cast<uint64_t>(1) << B) - 1;
+    for (int i = 0; i < 4; ++i) x = (x >> B) * c + (x & mask);
+    const uint64_t m = (static_cast<uint64_t>(1) << B) - c;
+    while (x >= m) x -= m;  // at most twice
+    return static_cast<uint32_t>(x);
 }
 
+template <int B = 32>
 MRG_HD constexpr uint32_t mulmod(uint32_t a, uint32_t b, uint32_t c) {
-    return fold64(static_cast<uint64_t>(a) * b, c);
+    return fold64<B>(static_cast<uint64_t>(a) * b, c);
 }
 
+template <int B = 32>
 MRG_HD constexpr uint32_t addmod(uint32_t a, uint32_t b, uint32_t c) {
-    return fold64(static_cast<uint64_t>(a) + b, c);
+    return fold64<B>(static_cast<uint64_t>(a) + b, c);
 }
 
 MRG_HD constexpr Mat3 identity() { return Mat3{{1, 0, 0, 0, 1, 0, 0, 0, 1}}; }
 
-// One-step matrices on (x[n-3], x[n-2], x[n-1]) -> (x[n-2], x[n-1], x[n]).
+// MRG32k3a one-step matrices on (x[n-3], x[n-2], x[n-1]) -> (x[n-2], x[n-1], x[n]).
 MRG_HD constexpr Mat3 step_matrix(int comp) {
     return comp == 0 ? Mat3{{0, 1, 0, 0, 0, 1, kM1 - kA13N, kA12, 0}}
                      : Mat3{{0, 1, 0, 0, 0, 1, kM2 - kA23N, 0, kA21}};
 }
 
-MRG_HD constexpr uint32_t comp_c(int comp) { return comp == 0 ? kC1 : kC2; }
+// MRG31k3p one-step matrices on (x[n-1], x[n-2], x[n-3]) -> (x[n], x[n-1], x[n-2]).
+MRG_HD constexpr Mat3 step_matrix31(int comp) {
+    return comp == 0 ? Mat3{{0, kB12, kB13, 1, 0, 0, 0, 1, 0}} : Mat3{{kB21, 0, kB23, 1, 0, 0, 0, 1, 0}};
+}
 
-MRG_HD constexpr Mat3 matmul(const Mat3& A, const Mat3& B, uint32_t c) {
+MRG_HD constexpr uint32_t comp_c(int comp) { return comp == 0 ? kC1 : kC2; }
+MRG_HD constexpr uint32_t comp_c31(int comp) { return comp == 0 ? kQ1 : kQ2; }
+
+template <int B = 32>
+MRG_HD constexpr Mat3 matmul(const Mat3& A, const Mat3& Bm, uint32_t c) {
     Mat3 C{};
     for (int r = 0; r < 3; ++r)
         for (int k = 0; k < 3; ++k) {
             uint32_t acc = 0;
-            for (int t = 0; t < 3; ++t) acc = addmod(acc, mulmod(A.a[r * 3 + t], B.a[t * 3 + k], c), c);
+            for (int t = 0; t < 3; ++t)
+                acc = addmod<B>(acc, mulmod<B>(A.a[r * 3 + t], Bm.a[t * 3 + k], c), c);
             C.a[r * 3 + k] = acc;
         }
     return C;
 }
 
 // A^(2^k) by k squarings.
+template <int B = 32>
 MRG_HD constexpr Mat3 pow2k(Mat3 A, int k, uint32_t c) {
-    for (int i = 0; i < k; ++i) A = matmul(A, A, c);
+    for (int i = 0; i < k; ++i) A = matmul<B>(A, A, c);
     return A;
 }
 
 // A^e for a 64-bit exponent.
+template <int B = 32>
 MRG_HD constexpr Mat3 matpow(Mat3 A, uint64_t e, uint32_t c) {
     Mat3 R = identity();
     while (e) {
-        if (e & 1) R = matmul(R, A, c);
-        A = matmul(A, A, c);
+        if (e & 1) R = matmul<B>(R, A, c);
+        A = matmul<B>(A, A, c);
         e >>= 1;
     }
     return R;
 }
 
-// v <- M v (mod 2^32 - c) on one component.
+// v <- M v (mod 2^B - c) on one component.
+template <int B = 32>
 MRG_HD constexpr void matvec(const Mat3& M, uint32_t v[3], uint32_t c) {
     uint32_t t[3] = {0, 0, 0};
     for (int r = 0; r < 3; ++r) {
         uint64_t acc = 0;
-        for (int k = 0; k < 3; ++k) acc += mulmod(M.a[r * 3 + k], v[k], c);
-        t[r] = fold64(acc, c);
+        for (int k = 0; k < 3; ++k) acc += mulmod<B>(M.a[r * 3 + k], v[k], c);
+        t[r] = fold64<B>(acc, c);
     }
     v[0] = t[0];
     v[1] = t[1];
@@ -116,29 +157,34 @@ MRG_HD constexpr void matvec(const Mat3& M, uint32_t v[3], uint32_t c) {
 }
 
 // Per-bit jump tables: step_pow2[j][b] = A_j^(2^b), stream_pow2[j][b] =
-// A_j^(2^(127+b)) (b < 64), substream[j] = A_j^(2^76).
+// A_j^(2^(Z+b)) (b < 64; Z = 127 or 134), substream[j] = A_j^(2^76 or 2^72).
 struct JumpTables {
     Mat3 step_pow2[2][64];
     Mat3 stream_pow2[2][64];
     Mat3 substream[2];
 };
 
+template <int G>
 MRG_HD constexpr JumpTables make_jump_tables() {
+    constexpr int B = G == kGen32k3a ? 32 : 31;
+    constexpr int zlog = G == kGen32k3a ? kStreamLog2 : kStreamLog2_31;
+    constexpr int slog = G == kGen32k3a ? kSubstreamLog2 : kSubstreamLog2_31;
     JumpTables T{};
     for (int j = 0; j < 2; ++j) {
-        uint32_t c = comp_c(j);
-        Mat3 A = step_matrix(j);
+        const uint32_t c = G == kGen32k3a ? comp_c(j) : comp_c31(j);
+        const Mat3 A1 = G == kGen32k3a ? step_matrix(j) : step_matrix31(j);
+        Mat3 A = A1;
         for (int b = 0; b < 64; ++b) {
             T.step_pow2[j][b] = A;
-            A = matmul(A, A, c);
+            A = matmul<B>(A, A, c);
         }
-        // continue squaring from A^(2^64) up to A^(2^127)
-        for (int b = 64; b < kStreamLog2; ++b) A = matmul(A, A, c);
+        // continue squaring from A^(2^64) up to A^(2^Z)
+        for (int b = 64; b < zlog; ++b) A = matmul<B>(A, A, c);
         for (int b = 0; b < 64; ++b) {
             T.stream_pow2[j][b] = A;
-            A = matmul(A, A, c);
+            A = matmul<B>(A, A, c);
         }
-        T.substream[j] = pow2k(step_matrix(j), kSubstreamLog2, c);
+        T.substream[j] = pow2k<B>(A1, slog, c);
     }
     return T;
 }

@@ -395,7 +395,7 @@ mrg_status mrg_server_create(const mrg_server_cfg* cfg, mrg_server** out) {
     // session streams: session i = streams i*S .. i*S+S-1 of one creator
     const uint64_t n_streams = static_cast<uint64_t>(S) * cfg->n_sessions;
     if (e == hipSuccess) e = hipMalloc(&s->streams_dev, n_streams * sizeof(mrg_stream));
-    if (e == hipSuccess) e = launch_create(s->streams_dev, n_streams, cr.s, nullptr);
+    if (e == hipSuccess) e = launch_create(kGen32k3a, s->streams_dev, n_streams, cr.s, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
 
     // lanes: workspace sized for max_batch requests, each cut into at most

@@ -54,7 +54,8 @@ __device__ __forceinline__ double log_factorial(int n) { return lgamma(static_ca
 // entries to tab[i*ld + j] (when tab is not null); returns -sum log(n_ij!)
 // summed row-major.  The engine advances (I-1)(J-1) steps.
 template <int MAXD, typename Engine>
-__device__ double sample_table(Engine& e, int I, int J, const int32_t* r, const int32_t* c, int32_t* tab, int ld) {
+__device__ double sample_table(Engine& e, double norm, int I, int J, const int32_t* r, const int32_t* c, int32_t* tab,
+                               int ld) {
     int32_t crem[MAXD];
     for (int j = 0; j < J; ++j) crem[j] = c[j];
     double stat = 0.0;
@@ -63,7 +64,7 @@ __device__ double sample_table(Engine& e, int I, int J, const int32_t* r, const 
         int64_t Np = 0;  // units left in columns j..J-1 over rows i..I-1
         for (int j = 0; j < J; ++j) Np += crem[j];
         for (int j = 0; j < J - 1; ++j) {
-            const double u = to_f64(e.step_rot()) * kNorm;
+            const double u = to_f64(e.step_rot()) * norm;
             const int x = hyper_invert(u, Np, crem[j], rrem);
             if (tab) tab[i * ld + j] = x;
             stat -= log_factorial(x);
@@ -82,11 +83,24 @@ __device__ double sample_table(Engine& e, int I, int J, const int32_t* r, const 
     return stat;
 }
 
+// The engine and the scale 1/(m1+1) of generator G.
+template <int G>
+struct GenOf {
+    using Engine = F64Engine;
+    static constexpr double norm = kNorm;
+};
+template <>
+struct GenOf<kGen31k3p> {
+    using Engine = Engine31;
+    static constexpr double norm = kNorm31;
+};
+
 // Tables t < n: shape I[t] x J[t] (<= 5 x 5), margins rows[t][5], cols[t][5],
 // from stream t; outputs tabs[t][5][5] (zero padded) and stats[t] (optional).
 // A table whose shape is out of range or whose margins are negative, differ
 // in total or total more than kTableMaxTotal gets zeros and a NaN statistic,
 // and its stream is left as it was (the checks also bound every loop).
+template <int G>
 __global__ void __launch_bounds__(256) tables_kernel(uint32_t* streams, uint64_t n, const int32_t* I,
                                                      const int32_t* J, const int32_t* rows, const int32_t* cols,
                                                      int32_t* tabs, double* stats) {
@@ -115,9 +129,9 @@ __global__ void __launch_bounds__(256) tables_kernel(uint32_t* streams, uint64_t
     uint32_t x[6];
 #pragma unroll
     for (int w = 0; w < 6; ++w) x[w] = rec[w];
-    F64Engine e;
+    typename GenOf<G>::Engine e;
     e.load(x);
-    const double stat = sample_table<5>(e, It, Jt, rows + t * 5, cols + t * 5, out, 5);
+    const double stat = sample_table<5>(e, GenOf<G>::norm, It, Jt, rows + t * 5, cols + t * 5, out, 5);
     if (stats) stats[t] = stat;
     e.save(x);
 #pragma unroll
@@ -141,6 +155,7 @@ struct FisherArgs {
 // Replicate b < B of the observed table's margins from stream b; counts the
 // replicates whose statistic is <= threshold (one atomic per wave; every
 // lane executes it, with the wave's count on lane 0 and 0 elsewhere).
+template <int G>
 __global__ void __launch_bounds__(256) fisher_kernel(FisherArgs a) {
     const uint64_t b = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint32_t lane = threadIdx.x & 63;
@@ -150,9 +165,9 @@ __global__ void __launch_bounds__(256) fisher_kernel(FisherArgs a) {
         uint32_t x[6];
 #pragma unroll
         for (int w = 0; w < 6; ++w) x[w] = rec[w];
-        F64Engine e;
+        typename GenOf<G>::Engine e;
         e.load(x);
-        const double stat = sample_table<kFisherMaxDim>(e, a.I, a.J, a.r, a.c, nullptr, 0);
+        const double stat = sample_table<kFisherMaxDim>(e, GenOf<G>::norm, a.I, a.J, a.r, a.c, nullptr, 0);
         hit = stat <= a.threshold;
         if (a.stats) a.stats[b] = stat;
         e.save(x);
@@ -163,14 +178,17 @@ __global__ void __launch_bounds__(256) fisher_kernel(FisherArgs a) {
     atomicAdd(a.count, lane == 0 ? wave_hits : 0ull);
 }
 
-hipError_t launch_tables(uint32_t* streams, uint64_t n, const int32_t* I, const int32_t* J, const int32_t* rows,
-                         const int32_t* cols, int32_t* tabs, double* stats, hipStream_t s) {
-    hipLaunchKernelGGL(tables_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, streams, n,
-                       I, J, rows, cols, tabs, stats);
+hipError_t launch_tables(int gen, uint32_t* streams, uint64_t n, const int32_t* I, const int32_t* J,
+                         const int32_t* rows, const int32_t* cols, int32_t* tabs, double* stats, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>((n + 255) / 256));
+    if (gen == kGen32k3a)
+        hipLaunchKernelGGL(tables_kernel<kGen32k3a>, grid, dim3(256), 0, s, streams, n, I, J, rows, cols, tabs, stats);
+    else
+        hipLaunchKernelGGL(tables_kernel<kGen31k3p>, grid, dim3(256), 0, s, streams, n, I, J, rows, cols, tabs, stats);
     return hipGetLastError();
 }
 
-hipError_t launch_fisher(uint32_t* streams, uint64_t B, int I, int J, const int32_t* r, const int32_t* c,
+hipError_t launch_fisher(int gen, uint32_t* streams, uint64_t B, int I, int J, const int32_t* r, const int32_t* c,
                          double threshold, unsigned long long* count, double* stats, hipStream_t s) {
     FisherArgs a{};
     a.streams = streams;
@@ -187,7 +205,9 @@ hipError_t launch_fisher(uint32_t* streams, uint64_t B, int I, int J, const int3
     hipLaunchKernelGGL(fisher_clear_kernel, dim3(1), dim3(1), 0, s, count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || B == 0) return e;
-    hipLaunchKernelGGL(fisher_kernel, dim3(static_cast<unsigned>((B + 255) / 256)), dim3(256), 0, s, a);
+    const dim3 grid(static_cast<unsigned>((B + 255) / 256));
+    if (gen == kGen32k3a) hipLaunchKernelGGL(fisher_kernel<kGen32k3a>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(fisher_kernel<kGen31k3p>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@ from conftest import ROOT
 import paper_2201_06604_amd as P
 
 M1, M2 = 4294967087, 4294944443
+P1, P2 = 2147483647, 2147462579
 HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
            if f.endswith(".h")]
 
@@ -66,9 +67,9 @@ def test_creator_init_rejects_invalid_seed():
     with pytest.raises(P.MrgError) as e:
         P.mrg_creator_init([1] * 6, gen=7)
     assert e.value.status == -1
-    with pytest.raises(P.MrgError) as e:
-        P.mrg_creator_init([1] * 6, gen=P.MRG_GEN_MRG31K3P)
-    assert e.value.status == -3
+    with pytest.raises(P.MrgError) as e:  # word 0 = p1 is not below MRG31k3p's m1
+        P.mrg_creator_init([2147483647, 1, 1, 1, 1, 1], gen=P.MRG_GEN_MRG31K3P)
+    assert e.value.status == -2
 
 
 @pytest.mark.parametrize("seed", [workloads.PAPER_SEED, list(workloads.random_seed())])
@@ -117,9 +118,9 @@ def test_generate_argument_validation_no_side_effects():
     assert f(256, 2**31 + 1, 10, P.MRG_UNIFORM, P.MRG_F64, 1.0, 256) == E
     # n = 0 is a no-op, even with null pointers
     assert f(0, 0, 0, P.MRG_UNIFORM, P.MRG_F64, 1.0, 0) == 0
-    # unsupported generator
+    # unknown generator
     L = P.lib()
-    assert L.mrg_generate(2, ctypes.c_void_p(256), 4, 10, 0, 0, 1.0, ctypes.c_void_p(256), None) == -3
+    assert L.mrg_generate(7, ctypes.c_void_p(256), 4, 10, 0, 0, 1.0, ctypes.c_void_p(256), None) == -1
 
 
 def test_launch_cfg_validation():
@@ -293,3 +294,50 @@ def test_tables_sample_validation():
     assert L.mrg_tables_sample(P.MRG_GEN_MRG32K3A, v, 5, v, v, v, v, ctypes.c_void_p(4098), None, None) == -1
     assert L.mrg_tables_sample(P.MRG_GEN_MRG32K3A, v, 5, v, v, v, v, v, ctypes.c_void_p(4100), None) == -1
     assert L.mrg_tables_sample(9, v, 5, v, v, v, v, v, None, None) == -1
+
+
+# ------------------------------------------------------------ MRG31k3p
+def test_mrg31k3p_host_creation_is_the_papers_table():
+    """Section 2.1: createStreamsCpu(4) from 12345 x 6 with MRG31k3p gives the
+    printed table (24 words), through the C ABI's host creation; the creator
+    then continues where the oracle's does."""
+    from conftest import read_golden
+    want = np.array([[int(v) for v in r] for r in read_golden("mrg31k3p_stream_table.txt")], dtype=np.uint32)
+    c = P.mrg_creator_init(workloads.PAPER_SEED, gen=P.MRG_GEN_MRG31K3P)
+    got = P.mrg_streams_create_host(c, 4, gen=P.MRG_GEN_MRG31K3P)
+    for k in range(3):
+        np.testing.assert_array_equal(got[:, 6 * k:6 * k + 6], want)
+    oc = np.array(workloads.PAPER_SEED, dtype=np.uint32)
+    O.create_streams(O.MRG31K3P, oc, 4)
+    np.testing.assert_array_equal(P.creator_words(c), oc)
+    more = P.mrg_streams_create_host(c, 50, gen=P.MRG_GEN_MRG31K3P)
+    np.testing.assert_array_equal(more, O.create_streams(O.MRG31K3P, oc, 50))
+
+
+def test_mrg31k3p_seed_rule_matches_oracle():
+    cases = [[12345] * 6, [P1 - 1] * 3 + [P2 - 1] * 3, [P1, 1, 1, 1, 1, 1], [1, 1, 1, P2, 1, 1],
+             [0, 0, 0, 5, 5, 5], [5, 5, 5, 0, 0, 0], [M1 - 1] * 6]
+    rnd = np.random.default_rng(9)
+    cases += [list(rnd.integers(0, 2**31, size=6)) for _ in range(50)]
+    for cse in cases:
+        ok = P.mrg_seed_check(cse, gen=P.MRG_GEN_MRG31K3P) == 0
+        assert ok == O.seed_valid(O.MRG31K3P, cse), cse
+
+
+def test_mrg31k3p_import_checks_its_moduli():
+    """A saved MRG31k3p state with a word in [p1, m1) is corrupt for MRG31k3p
+    (valid for MRG32k3a); a saved MRG32k3a buffer is refused as MRG31k3p."""
+    rec = np.full((1, 18), 7, dtype=np.uint32)
+    rec[0, 0] = P1
+    buf = _saved(1, gen=2, records=rec)
+    st = P.lib().mrg_streams_import(2, buf, len(buf), ctypes.c_void_p(4096), 1, None, None, None)
+    assert st == -6
+    buf = _saved(1, gen=1, records=np.full((1, 18), 7, dtype=np.uint32))
+    st = P.lib().mrg_streams_import(2, buf, len(buf), ctypes.c_void_p(4096), 1, None, None, None)
+    assert st == -6
+
+
+def test_batch_rejects_mrg31k3p():
+    req = (P.mrg_request * 1)()
+    plan = ctypes.c_void_p()
+    assert P.lib().mrg_batch_plan_create(2, req, 1, None, ctypes.byref(plan)) == -3
