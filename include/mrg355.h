@@ -49,8 +49,13 @@ typedef enum {
 } mrg_status;
 
 /* Generators.  MRG32k3a: components mod m1 = 2^32-209 and m2 = 2^32-22853,
- * streams 2^127 apart, substreams 2^76 apart.  (Id 2 is reserved for the
- * paper's own MRG31k3p.) */
+ * streams 2^127 apart, substreams 2^76 apart, state words oldest-first
+ * (x1[n-3], x1[n-2], x1[n-1], x2[n-3], ...).  MRG31k3p (the paper's own,
+ * Section 2): m1 = 2^31-1, m2 = 2^31-21069, streams 2^134 apart (Section
+ * 2.1), substreams 2^72 apart, words newest-first (x1[n-1], x1[n-2],
+ * x1[n-3], x2[n-1], ...) as in the stream table of Section 2.1, uniforms
+ * z / 2^31.  Both run every stream, generate, save/restore and table call;
+ * the batch and server calls run MRG32k3a only (MRG_E_UNSUPPORTED). */
 typedef enum { MRG_GEN_MRG32K3A = 1, MRG_GEN_MRG31K3P = 2 } mrg_generator;
 
 /* Distributions (Sections 2.2, 3.1, 3.2):

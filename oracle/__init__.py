@@ -66,6 +66,8 @@ def lib():
                 "orc_generate_range": (c_int, [c_int, u32p, c_u64, c_u64, c_int, c_int, c_dbl, vp,
                                                c_u64, c_u64]),
                 "orc_generate": (c_int, [c_int, u32p, c_u64, c_u64, c_int, c_int, c_dbl, vp]),
+                "orc_generate_paper": (c_int, [c_int, u32p, c_u64, c_u64, c_u64, c_u64, c_u64, c_u64,
+                                               c_int, c_int, c_dbl, vp]),
                 "orc_hyper_invert": (c_int, [c_dbl, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]),
                 "orc_table_sample_ld": (c_int, [c_int, u32p, c_int, c_int, i32p, i32p, i32p, c_int]),
                 "orc_table_stat_ld": (c_dbl, [c_int, c_int, i32p, c_int]),
@@ -220,6 +222,20 @@ def generate(gen, streams, n, dist=UNIFORM, dtype=F64, param=1.0, threads=1):
         t.join()
     assert all(rc == 0 for rc in rcs)
     return out
+
+
+def generate_paper(gen, streams, nrow, ncol, G0, G1, dist=UNIFORM, dtype=F64, param=1.0, npad=None,
+                   fill=0):
+    """The paper's kernel geometry: an nrow x ncol output (row stride npad,
+    padding left at `fill`) from a G0 x G1 lattice of work-items (Listing 1 /
+    Listing 2).  Returns the nrow x npad buffer; streams advance in place."""
+    npad = ncol if npad is None else npad
+    out = np.full(nrow * npad, fill, dtype=_NP_DTYPE[dtype])
+    rc = lib().orc_generate_paper(gen, _u32p(streams), streams.shape[0], nrow, ncol, npad, G0, G1, dist,
+                                  dtype, param, out.ctypes.data_as(ctypes.c_void_p))
+    if rc:
+        raise ValueError("invalid geometry")
+    return out.reshape(nrow, npad)
 
 
 # ------------------------------------------------------------- Fisher tables

@@ -413,3 +413,70 @@ int orc_generate(int gen, uint32_t* streams, uint64_t S, uint64_t n, int dist, i
                  double param, void* out) {
     return orc_generate_range(gen, streams, S, n, dist, dtype, param, out, 0, S);
 }
+
+/* ------------------------------------------------------------------------ */
+/* The paper's work-item geometry (Listing 1 of Section 2.2, Listing 2 of    */
+/* Section 3.1)                                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Stream of work-item (g0, g1) on a G0 x G1 lattice: uniforms and integers
+ * take g0 + G0 g1 (Listing 1); normals take g0 G1 + g1 (Listing 2), and so do
+ * exponentials (reading: the 2 x 4 matrix printed in Section 3.2 is only
+ * reproduced with this index).                                             */
+static uint64_t paper_stream(int dist, uint64_t g0, uint64_t g1, uint64_t G0, uint64_t G1) {
+    if (dist == ORC_UNIFORM || dist == ORC_RAW) return g0 + G0 * g1;
+    return g0 * G1 + g1;
+}
+
+/* An Nrow x Ncol output inside a row-major Nrow x Npad buffer.  Work-item
+ * (g0, g1) owns the cells (r, c) with r = g0 (mod G0) and c = g1 (mod G1),
+ * visits them rows ascending and, within a row, columns ascending, and puts
+ * its next value at out[r * Npad + c].  For normals the work-items (g0, 2p)
+ * and (g0, 2p + 1) form a pair: at each visit the first draws U1 from its
+ * stream and the second draws U2 from its own; X goes to the first one's
+ * cell, Y to the second one's (Algorithm 1; Listing 2 pairs the two through
+ * local memory).  Normals need G1 and Ncol even, so that both members of a
+ * pair make the same number of visits.  Streams not used stay as they are;
+ * cells outside the Nrow x Ncol block are not written.  Returns -1 on an
+ * invalid geometry (nothing is changed then).                               */
+int orc_generate_paper(int gen, uint32_t* streams, uint64_t n_streams, uint64_t Nrow, uint64_t Ncol,
+                       uint64_t Npad, uint64_t G0, uint64_t G1, int dist, int dtype, double param,
+                       void* out) {
+    const orc_gen* g = gen_of(gen);
+    if (!g || G0 == 0 || G1 == 0 || Npad < Ncol || n_streams < G0 * G1) return -1;
+    if (dist == ORC_NORMAL && (G1 % 2 || Ncol % 2)) return -1;
+    const double norm = orc_norm(gen);
+    for (uint64_t g0 = 0; g0 < G0; ++g0) {
+        for (uint64_t g1 = 0; g1 < G1; ++g1) {
+            if (dist == ORC_NORMAL && g1 % 2) continue; /* the pair's second member */
+            uint32_t* a = streams + paper_stream(dist, g0, g1, G0, G1) * ORC_REC + ORC_CUR;
+            int64_t xa[2][3], xb[2][3];
+            to_internal(g, a, xa);
+            uint32_t* b = NULL;
+            if (dist == ORC_NORMAL) {
+                b = streams + paper_stream(dist, g0, g1 + 1, G0, G1) * ORC_REC + ORC_CUR;
+                to_internal(g, b, xb);
+            }
+            for (uint64_t r = g0; r < Nrow; r += G0) {
+                for (uint64_t c = g1; c < Ncol; c += G1) {
+                    if (dist == ORC_NORMAL) {
+                        double u1 = (double)step(g, xa) * norm;
+                        double u2 = (double)step(g, xb) * norm;
+                        double X, Y;
+                        orc_box_muller(u1, u2, &X, &Y);
+                        put(out, r * Npad + c, dtype, X, 0, dist);
+                        put(out, r * Npad + c + 1, dtype, Y, 0, dist);
+                    } else {
+                        uint64_t z = step(g, xa);
+                        double u = (double)z * norm;
+                        double v = dist == ORC_EXPONENTIAL ? orc_exponential(u, param) : u;
+                        put(out, r * Npad + c, dtype, v, z, dist);
+                    }
+                }
+            }
+            to_external(g, xa, a);
+            if (b) to_external(g, xb, b);
+        }
+    }
+    return 0;
+}
