@@ -191,6 +191,33 @@ mrg_status mrg_streams_import(mrg_generator gen, const void* host_buf, size_t le
                               size_t n, size_t* n_out, mrg_creator* creator, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * The paper's own kernel geometry (Listing 1 of Section 2.2, Listing 2 of
+ * Section 3.1), for code that relies on where clrng puts each number.
+ *
+ * The output is an nrow x ncol block of a row-major buffer with row stride
+ * npad (elements; npad >= ncol; the other npad - ncol columns are not
+ * written).  A g0size x g1size lattice of work-items (clrng's Nglobal) covers
+ * it: work-item (g0, g1) owns the cells (g0 + i*g0size, g1 + j*g1size),
+ * visits them row by row (i ascending, then j ascending) and stores its next
+ * value in each.  Its stream is number g0 + g0size*g1 for MRG_UNIFORM and
+ * MRG_RAW (Listing 1) and g0*g1size + g1 for MRG_NORMAL and MRG_EXPONENTIAL
+ * (Listing 2; the exponential matrix printed in Section 3.2 needs this
+ * index).  Normals pair the work-items (g0, 2p) and (g0, 2p+1): each visit
+ * takes U1 from the first one's stream and U2 from the second one's, X goes
+ * to the first one's cell and Y to the second one's (Algorithm 1); g1size
+ * and ncol must be even.  A vector is one row (nrow = 1), as in the printed
+ * runifGpu example.
+ *
+ * Needs n_streams >= g0size*g1size; a stream advances by the number of
+ * visits of its work-item and the others do not move.  Values and rounding
+ * are those of mrg_generate (f32 uniforms round toward zero).  nrow, ncol
+ * < 2^31; nrow == 0 or ncol == 0 is a no-op.
+ * ------------------------------------------------------------------------ */
+mrg_status mrg_generate_paper(mrg_generator gen, mrg_stream* dev, size_t n_streams, uint64_t nrow, uint64_t ncol,
+                              uint64_t npad, uint32_t g0size, uint32_t g1size, mrg_dist dist, mrg_dtype dtype,
+                              double param, void* dev_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * The Monte-Carlo Fisher test of Section 4: random contingency tables with
  * fixed margins, one stream per table.  Entries are drawn row by row in
  * row-major order, each by inversion of its hypergeometric distribution given

@@ -118,6 +118,8 @@ def lib():
             "mrg_batch_request_times": (i32, [vp, vp, ctypes.POINTER(ctypes.c_uint64), vp]),
             "mrg_batch_autotune": (i32, [vp, vp, sz, vp, ctypes.POINTER(mrg_batch_cfg),
                                          ctypes.POINTER(ctypes.c_double)]),
+            "mrg_generate_paper": (i32, [i32, vp, sz, u64, u64, u64, ctypes.c_uint32, ctypes.c_uint32, i32, i32,
+                                         ctypes.c_double, vp, vp]),
             "mrg_tables_sample": (i32, [i32, vp, sz, vp, vp, vp, vp, vp, vp, vp]),
             "mrg_fisher_sim": (i32, [i32, vp, u64, i32, i32, ctypes.POINTER(ctypes.c_int32), vp, vp,
                                      ctypes.POINTER(ctypes.c_double), vp]),
@@ -146,7 +148,7 @@ EXPORTED = ["mrg_abi_version", "mrg_status_string", "mrg_last_error", "mrg_seed_
             "mrg_creator_init", "mrg_streams_create_host", "mrg_streams_create_device",
             "mrg_streams_reset", "mrg_streams_advance", "mrg_generate", "mrg_generate_ex",
             "mrg_streams_export_size", "mrg_streams_export", "mrg_streams_import",
-            "mrg_tables_sample", "mrg_fisher_sim", "mrg_fisher_pvalue",
+            "mrg_generate_paper", "mrg_tables_sample", "mrg_fisher_sim", "mrg_fisher_pvalue",
             "mrg_batch_plan_create", "mrg_batch_plan_destroy", "mrg_batch_workspace_size",
             "mrg_batch_tile_count", "mrg_batch_upload", "mrg_batch_launch",
             "mrg_batch_request_times", "mrg_batch_autotune", "mrg_now_ns", "mrg_server_create",
@@ -297,6 +299,23 @@ def mrg_streams_import(data, out, creator=None, gen=MRG_GEN_MRG32K3A, stream=Non
                                     ctypes.byref(creator) if creator is not None else None,
                                     _stream(stream)))
     return cnt.value
+
+
+def mrg_generate_paper(streams, nrow, ncol, G0, G1, dist=MRG_UNIFORM, dtype=MRG_F64, param=1.0, out=None,
+                       npad=None, gen=MRG_GEN_MRG32K3A, stream=None):
+    """clrng's placement (Listing 1 / Listing 2): an nrow x ncol block of an
+    nrow x npad buffer from a G0 x G1 lattice of work-items (Nglobal).
+    Returns the nrow x npad tensor (columns past ncol untouched)."""
+    import torch
+    npad = ncol if npad is None else npad
+    if out is None:
+        out = torch.empty((max(nrow, 1), max(npad, 1)), dtype=getattr(torch, _TORCH_DT[dtype]),
+                          device=streams.device)
+    if out.numel() < nrow * npad or not out.is_contiguous():
+        raise ValueError("out must be a contiguous buffer of nrow * npad elements")
+    _check(lib().mrg_generate_paper(gen, _dptr(streams), streams.shape[0], nrow, ncol, npad, G0, G1, dist, dtype,
+                                    param, _dptr(out), _stream(stream)))
+    return out
 
 
 def mrg_tables_sample(streams, I, J, rows, cols, tables=None, stats=None, n=None,

@@ -226,6 +226,51 @@ mrg_status mrg_generate(mrg_generator gen, mrg_stream* dev, size_t n_streams, ui
     return mrg_generate_ex(gen, dev, n_streams, n, dist, dtype, param, dev_out, nullptr, stream);
 }
 
+mrg_status mrg_generate_paper(mrg_generator gen, mrg_stream* dev, size_t n_streams, uint64_t nrow, uint64_t ncol,
+                              uint64_t npad, uint32_t g0size, uint32_t g1size, mrg_dist dist, mrg_dtype dtype,
+                              double param, void* dev_out, hipStream_t stream) {
+    if (mrg_status st = check_gen(gen)) return st;
+    if (dist != MRG_UNIFORM && dist != MRG_NORMAL && dist != MRG_EXPONENTIAL && dist != MRG_RAW)
+        return fail(MRG_E_INVALID_ARG, "unknown distribution %d", static_cast<int>(dist));
+    if (dtype != MRG_F64 && dtype != MRG_F32 && dtype != MRG_U32)
+        return fail(MRG_E_INVALID_ARG, "unknown dtype %d", static_cast<int>(dtype));
+    if ((dist == MRG_RAW) != (dtype == MRG_U32))
+        return fail(MRG_E_INVALID_ARG, "MRG_RAW pairs with MRG_U32 only, and MRG_U32 with MRG_RAW only");
+    if (dist == MRG_EXPONENTIAL && !(std::isfinite(param) && param > 0.0))
+        return fail(MRG_E_INVALID_ARG, "exponential rate must be finite and > 0");
+    if (g0size == 0 || g1size == 0) return fail(MRG_E_INVALID_ARG, "the work-item lattice must be non-empty");
+    if (n_streams > (static_cast<size_t>(1) << 31)) return fail(MRG_E_INVALID_ARG, "n_streams above 2^31");
+    if (static_cast<uint64_t>(g0size) * g1size > n_streams)
+        return fail(MRG_E_INVALID_ARG, "%u x %u work-items need as many streams, %zu given", g0size, g1size,
+                    n_streams);
+    if (npad < ncol) return fail(MRG_E_INVALID_ARG, "npad below ncol");
+    if (nrow >= (1ull << 31) || ncol >= (1ull << 31)) return fail(MRG_E_INVALID_ARG, "nrow and ncol below 2^31");
+    if (nrow && npad > (1ull << 62) / nrow) return fail(MRG_E_INVALID_ARG, "nrow * npad too large");
+    if (dist == MRG_NORMAL && (g1size % 2 || ncol % 2))
+        return fail(MRG_E_INVALID_ARG, "normals pair work-items along the second dimension: G1 and ncol must be even");
+    if (nrow == 0 || ncol == 0) return ok();
+    if (!dev || !dev_out) return fail(MRG_E_INVALID_ARG, "NULL stream or output pointer");
+    const size_t esz = dtype == MRG_F64 ? 8 : 4;
+    if (reinterpret_cast<uintptr_t>(dev_out) % esz)
+        return fail(MRG_E_INVALID_ARG, "output not aligned to its element size");
+    if (reinterpret_cast<uintptr_t>(dev) % 4) return fail(MRG_E_INVALID_ARG, "streams misaligned");
+    PaperLaunch L{};
+    L.streams = reinterpret_cast<uint32_t*>(dev);
+    L.out = dev_out;
+    L.npad = npad;
+    L.nrow = static_cast<uint32_t>(nrow);
+    L.ncol = static_cast<uint32_t>(ncol);
+    L.G0 = g0size;
+    L.G1 = g1size;
+    L.dist = static_cast<int>(dist);
+    L.dtype = static_cast<int>(dtype);
+    L.param = dist == MRG_EXPONENTIAL ? 1.0 / param : 1.0;
+    plan_paper(L);
+    hipError_t e = launch_paper(L, gid(gen), stream);
+    if (e != hipSuccess) return hip_fail(e, "paper-geometry launch");
+    return ok();
+}
+
 mrg_status mrg_tables_sample(mrg_generator gen, mrg_stream* dev_streams, size_t n, const int32_t* dev_I,
                              const int32_t* dev_J, const int32_t* dev_rows, const int32_t* dev_cols,
                              int32_t* dev_tables, double* dev_stats, hipStream_t stream) {

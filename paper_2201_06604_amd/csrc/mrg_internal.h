@@ -123,6 +123,22 @@ hipError_t launch_tables(int gen, uint32_t* streams, uint64_t n, const int32_t* 
 hipError_t launch_fisher(int gen, uint32_t* streams, uint64_t B, int I, int J, const int32_t* r, const int32_t* c,
                          double threshold, unsigned long long* count, double* stats, hipStream_t s);
 
+// The paper's work-item geometry (Listing 1 / Listing 2): see mrg_generate_paper.
+struct PaperLaunch {
+    uint32_t* streams;
+    void* out;
+    uint64_t npad;       // row stride of out, in elements
+    uint32_t nrow, ncol; // the block written
+    uint32_t G0, G1;     // work-item lattice
+    uint32_t lanes_g1;   // G1, or G1/2 pairs for normals
+    uint32_t rows_per;   // work-item rows per lane
+    uint32_t n_rb;       // row blocks per work-item
+    int dist, dtype;
+    double param;        // 1/rate for exponentials
+};
+void plan_paper(PaperLaunch& L);
+hipError_t launch_paper(const PaperLaunch& L, int gen, hipStream_t s);
+
 // Host-side jump math (same tables the device uses).
 void host_jump_pow2(int gen, uint32_t state[6], uint64_t k, bool stream_tables);  // A^(k [* Z]) state
 

@@ -765,4 +765,165 @@ hipError_t launch_generate(const GenLaunch& L, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ------------------------------------------------- the paper's geometry
+// Listing 1 (Section 2.2) and Listing 2 (Section 3.1): a G0 x G1 lattice of
+// work-items; work-item (g0, g1) owns the cells (g0 + i G0, g1 + j G1) of
+// the nrow x ncol output (row stride npad) and visits them row by row.  Its
+// stream is g0 + G0 g1 for uniforms and integers, g0 G1 + g1 for normals and
+// exponentials.  Normals pair the work-items (g0, 2p) and (g0, 2p+1): one
+// lane runs both streams, U1 from the first, U2 from the second, X and Y to
+// the two adjacent cells.
+//
+// A lane runs one work-item (or pair) over a block of its rows, jumping its
+// stream(s) to the block's first visit; lanes with neighbouring g1 write
+// neighbouring columns of a row.  With one row block the lane writes the
+// state back; otherwise paper_finalize_kernel does, after the launch.
+template <int G>
+struct EngineOf {
+    using T = F64Engine;
+};
+template <>
+struct EngineOf<kGen31k3p> {
+    using T = Engine31;
+};
+
+__device__ __forceinline__ uint64_t paper_stream_of(int dist, uint32_t g0, uint32_t g1, uint32_t G0, uint32_t G1) {
+    return (dist == kUniform || dist == kRaw) ? g0 + static_cast<uint64_t>(G0) * g1
+                                              : static_cast<uint64_t>(g0) * G1 + g1;
+}
+
+template <int DIST, int DTYPE, int G>
+__global__ void __launch_bounds__(256) paper_kernel(PaperLaunch L) {
+    using Engine = typename EngineOf<G>::T;
+    using T = typename ElemOf<DTYPE>::T;
+    const uint64_t id = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t per_block = static_cast<uint64_t>(L.G0) * L.lanes_g1;
+    if (id >= per_block * L.n_rb) return;
+    const uint32_t rb = static_cast<uint32_t>(id / per_block);
+    const uint64_t rem = id % per_block;
+    const uint32_t g0 = static_cast<uint32_t>(rem / L.lanes_g1);
+    const uint32_t h = static_cast<uint32_t>(rem % L.lanes_g1);
+    const uint32_t g1 = DIST == kNormal ? 2 * h : h;
+    if (g0 >= L.nrow || g1 >= L.ncol) return;  // the work-item owns no cell
+    const uint32_t nr = (L.nrow - 1 - g0) / L.G0 + 1;
+    const uint32_t nc = (L.ncol - 1 - g1) / L.G1 + 1;
+    const uint32_t i0 = rb * L.rows_per;
+    if (i0 >= nr) return;
+    const uint32_t i1 = min(nr, i0 + L.rows_per);
+    const uint64_t first = static_cast<uint64_t>(i0) * nc;  // visits before this block
+
+    uint32_t* ra = L.streams + paper_stream_of(DIST, g0, g1, L.G0, L.G1) * 18;
+    uint32_t* rb_rec = DIST == kNormal ? L.streams + paper_stream_of(DIST, g0, g1 + 1, L.G0, L.G1) * 18 : ra;
+    uint32_t x[6];
+    Engine ea, eb;
+#pragma unroll
+    for (int w = 0; w < 6; ++w) x[w] = ra[w];
+    if (first) dev_jump<G>(x, first);
+    ea.load(x);
+    if constexpr (DIST == kNormal) {
+#pragma unroll
+        for (int w = 0; w < 6; ++w) x[w] = rb_rec[w];
+        if (first) dev_jump<G>(x, first);
+        eb.load(x);
+    }
+    T* out = static_cast<T*>(L.out);
+    const double inv_rate = L.param;
+    for (uint32_t i = i0; i < i1; ++i) {
+        T* row = out + static_cast<uint64_t>(g0 + static_cast<uint64_t>(i) * L.G0) * L.npad;
+        for (uint32_t j = 0, c = g1; j < nc; ++j, c += L.G1) {
+            if constexpr (DIST == kNormal) {
+                auto z1 = ea.step_rot();
+                auto z2 = eb.step_rot();
+                double xv, yv;
+                box_muller<G>(z1, z2, xv, yv);
+                __builtin_nontemporal_store(narrow<DTYPE>(xv), row + c);
+                __builtin_nontemporal_store(narrow<DTYPE>(yv), row + c + 1);
+            } else {
+                __builtin_nontemporal_store(value1<DIST, DTYPE, G>(ea.step_rot(), inv_rate), row + c);
+            }
+        }
+    }
+    if (L.n_rb == 1) {
+        ea.save(x);
+#pragma unroll
+        for (int w = 0; w < 6; ++w) ra[w] = x[w];
+        if constexpr (DIST == kNormal) {
+            eb.save(x);
+#pragma unroll
+            for (int w = 0; w < 6; ++w) rb_rec[w] = x[w];
+        }
+    }
+}
+
+// After a launch with several row blocks: every used stream advances by its
+// work-item's number of visits.
+template <int G>
+__global__ void __launch_bounds__(256) paper_finalize_kernel(PaperLaunch L) {
+    const uint64_t id = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (id >= static_cast<uint64_t>(L.G0) * L.lanes_g1) return;
+    const uint32_t g0 = static_cast<uint32_t>(id / L.lanes_g1);
+    const uint32_t h = static_cast<uint32_t>(id % L.lanes_g1);
+    const bool normal = L.dist == kNormal;
+    const uint32_t g1 = normal ? 2 * h : h;
+    if (g0 >= L.nrow || g1 >= L.ncol) return;
+    const uint64_t visits = static_cast<uint64_t>((L.nrow - 1 - g0) / L.G0 + 1) * ((L.ncol - 1 - g1) / L.G1 + 1);
+    for (int k = 0; k < (normal ? 2 : 1); ++k) {
+        uint32_t* rec = L.streams + paper_stream_of(L.dist, g0, g1 + k, L.G0, L.G1) * 18;
+        uint32_t x[6];
+#pragma unroll
+        for (int w = 0; w < 6; ++w) x[w] = rec[w];
+        for (int b = 0; b < 64; ++b)
+            if ((visits >> b) & 1) dev_apply<G>(dev_tab<G>().step_pow2[0][b], dev_tab<G>().step_pow2[1][b], x);
+#pragma unroll
+        for (int w = 0; w < 6; ++w) rec[w] = x[w];
+    }
+}
+
+void plan_paper(PaperLaunch& L) {
+    L.lanes_g1 = L.dist == kNormal ? L.G1 / 2 : L.G1;
+    const uint64_t nr_max = (static_cast<uint64_t>(L.nrow) + L.G0 - 1) / L.G0;
+    const uint64_t items = static_cast<uint64_t>(L.G0) * L.lanes_g1;
+    // about 2^20 lanes (16 waves per SIMD), at least one row per lane
+    uint64_t blocks = ((1ull << 20) + items - 1) / items;
+    if (blocks > nr_max) blocks = nr_max;
+    if (blocks < 1) blocks = 1;
+    L.rows_per = static_cast<uint32_t>((nr_max + blocks - 1) / blocks);
+    if (L.rows_per == 0) L.rows_per = 1;
+    L.n_rb = static_cast<uint32_t>((nr_max + L.rows_per - 1) / L.rows_per);
+    if (L.n_rb == 0) L.n_rb = 1;
+}
+
+template <int DIST, int DTYPE>
+static hipError_t launch_paper_t(const PaperLaunch& L, int gen, hipStream_t s) {
+    const uint64_t lanes = static_cast<uint64_t>(L.G0) * L.lanes_g1 * L.n_rb;
+    const dim3 grid(static_cast<unsigned>((lanes + 255) / 256));
+    if (gen == kGen32k3a) hipLaunchKernelGGL((paper_kernel<DIST, DTYPE, kGen32k3a>), grid, dim3(256), 0, s, L);
+    else hipLaunchKernelGGL((paper_kernel<DIST, DTYPE, kGen31k3p>), grid, dim3(256), 0, s, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_paper(const PaperLaunch& L, int gen, hipStream_t s) {
+    hipError_t e;
+    switch (L.dist) {
+        case kUniform:
+            e = L.dtype == kF64 ? launch_paper_t<kUniform, kF64>(L, gen, s) : launch_paper_t<kUniform, kF32>(L, gen, s);
+            break;
+        case kNormal:
+            e = L.dtype == kF64 ? launch_paper_t<kNormal, kF64>(L, gen, s) : launch_paper_t<kNormal, kF32>(L, gen, s);
+            break;
+        case kExponential:
+            e = L.dtype == kF64 ? launch_paper_t<kExponential, kF64>(L, gen, s)
+                                : launch_paper_t<kExponential, kF32>(L, gen, s);
+            break;
+        default:
+            e = launch_paper_t<kRaw, kU32>(L, gen, s);
+    }
+    if (e != hipSuccess || L.n_rb == 1) return e;
+    const uint64_t items = static_cast<uint64_t>(L.G0) * L.lanes_g1;
+    const dim3 grid(static_cast<unsigned>((items + 255) / 256));
+    if (gen == kGen32k3a) hipLaunchKernelGGL(paper_finalize_kernel<kGen32k3a>, grid, dim3(256), 0, s, L);
+    else hipLaunchKernelGGL(paper_finalize_kernel<kGen31k3p>, grid, dim3(256), 0, s, L);
+    return hipGetLastError();
+}
+
 }  // namespace mrg355

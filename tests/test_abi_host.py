@@ -341,3 +341,25 @@ def test_batch_rejects_mrg31k3p():
     req = (P.mrg_request * 1)()
     plan = ctypes.c_void_p()
     assert P.lib().mrg_batch_plan_create(2, req, 1, None, ctypes.byref(plan)) == -3
+
+
+def test_generate_paper_validation():
+    """Lattice, stream count, padding, pairing and size checks come before
+    any launch."""
+    L = P.lib()
+    v = ctypes.c_void_p(4096)
+
+    def st(n_streams, nrow, ncol, npad, G0, G1, dist=0, dtype=0, param=1.0, out=v, gen=1):
+        return L.mrg_generate_paper(gen, v, n_streams, nrow, ncol, npad, G0, G1, dist, dtype, param, out, None)
+
+    assert st(4, 2, 4, 4, 0, 2) == -1           # empty lattice
+    assert st(4, 2, 4, 4, 3, 2) == -1           # 6 work-items, 4 streams
+    assert st(4, 2, 4, 3, 2, 2) == -1           # npad < ncol
+    assert st(4, 2, 3, 4, 1, 2, dist=1) == -1   # normals: odd ncol
+    assert st(4, 2, 4, 4, 1, 3, dist=1) == -1   # normals: odd G1
+    assert st(4, 2, 4, 4, 2, 2, dist=3, dtype=0) == -1
+    assert st(4, 2, 4, 4, 2, 2, dist=2, param=0.0) == -1
+    assert st(4, 1 << 31, 4, 4, 2, 2) == -1
+    assert st(4, 2, 4, 4, 2, 2, out=ctypes.c_void_p(4100)) == -1
+    assert st(4, 2, 4, 4, 2, 2, gen=5) == -1
+    assert st(4, 0, 4, 4, 2, 2, out=None) == 0  # empty block: no-op
