@@ -24,6 +24,14 @@
  * multiply, one rounded divide).  The entry is the smallest x with
  * u * W <= w(lo) + ... + w(x), W = w(lo) + ... + w(hi), sums taken in order.
  * Built with -ffp-contract=off.
+ *
+ * The weights can exceed the double range: w(mode)/w(lo) = pmf(mode)/pmf(lo)
+ * passes 2^1024 for some entries of the day-of-week table of Section 4.2.
+ * They are therefore carried with an extended exponent: whenever a weight
+ * exceeds 2^600, it and the running sum are multiplied by 2^-600 (exact), and
+ * the search compares u * W with the running sum brought to W's scale.  Every
+ * mantissa is the one of the same double-precision operations on an unbounded
+ * exponent range, so nothing changes where nothing overflowed.
  */
 #include <float.h>
 #include <math.h>
@@ -35,30 +43,47 @@ double orc_norm(int gen);
 
 enum { FT_MAX = 5, FT_DIM = 32 };
 
+#define ORC_BIG 0x1p600
+#define ORC_SCALE_EXP 600
+
 /* One entry by inversion of its conditional distribution. */
 int orc_hyper_invert(double u, int64_t Np, int64_t K, int64_t n) {
     int64_t lo = n - (Np - K);
     if (lo < 0) lo = 0;
     int64_t hi = n < K ? n : K;
     if (hi <= lo) return (int)lo;
+    /* W = w(lo) + ... + w(hi); `scales` counts the 2^-600 rescalings */
     double W = 0.0, w = 1.0;
+    int scales = 0;
     for (int64_t x = lo; x <= hi; ++x) {
         W += w;
         if (x < hi) {
             double num = (double)((K - x) * (n - x));
             double den = (double)((x + 1) * (Np - K - n + x + 1));
             w = w * num / den;
+            if (w > ORC_BIG) {
+                w = ldexp(w, -ORC_SCALE_EXP);
+                W = ldexp(W, -ORC_SCALE_EXP);
+                ++scales;
+            }
         }
     }
     double target = u * W;
+    /* the same running sums again, each compared at W's scale */
     double s = 0.0;
     w = 1.0;
+    int done = 0;
     for (int64_t x = lo; x <= hi; ++x) {
         s += w;
-        if (target <= s) return (int)x;
+        if (target <= ldexp(s, -ORC_SCALE_EXP * (scales - done))) return (int)x;
         double num = (double)((K - x) * (n - x));
         double den = (double)((x + 1) * (Np - K - n + x + 1));
         w = w * num / den;
+        if (w > ORC_BIG) {
+            w = ldexp(w, -ORC_SCALE_EXP);
+            s = ldexp(s, -ORC_SCALE_EXP);
+            ++done;
+        }
     }
     return (int)hi;
 }

@@ -47,7 +47,8 @@ def _hyper_cdf(Np, K, n):
 
 
 @pytest.mark.parametrize("Np,K,n", [(10, 4, 3), (30, 12, 17), (200, 5, 150), (400, 180, 200),
-                                    (57, 57, 20), (57, 0, 20), (12, 7, 12), (1000, 300, 400)])
+                                    (57, 57, 20), (57, 0, 20), (12, 7, 12), (1000, 300, 400),
+                                    (1983, 589, 1177)])  # w(mode)/w(lo) > 2^1024
 def test_inversion_is_the_hypergeometric_quantile(Np, K, n):
     """The entry sampled from u is the smallest x with u <= F(x), F the exact
     hypergeometric cdf (rational arithmetic), away from the cdf's jumps."""
@@ -128,3 +129,52 @@ def test_month_pvalue_near_paper():
     p = (1 + cnt) / (B + 1)
     se = math.sqrt(0.403 * 0.597 / B)
     assert abs(p - 0.403) < 4 * se, p
+
+
+@pytest.mark.parametrize("name", ["fisher_month.txt", "fisher_week.txt"])
+def test_cell_moments_on_paper_tables(name):
+    """Under the null each cell is hypergeometric: mean r_i c_j / N and
+    variance r_i c_j (N - r_i)(N - c_j) / (N^2 (N - 1)).  3000 oracle tables
+    with the margins of the paper's tables must agree cell by cell (|z| < 5
+    for the mean, variance within 25%).  Overflowing weights put one cell of
+    the day-of-week table 9 standard errors off."""
+    tab = _golden_table(name).astype(np.int64)
+    r, c, N = tab.sum(axis=1), tab.sum(axis=0), int(tab.sum())
+    B = 3000
+    rec = O.create_streams(GEN, workloads.random_seed(13), B)
+    acc = np.zeros(tab.shape)
+    acc2 = np.zeros(tab.shape)
+    for b in range(B):
+        t = O.table_sample(GEN, rec[b, :6].copy(), r.astype(np.int32), c.astype(np.int32)).astype(np.float64)
+        acc += t
+        acc2 += t * t
+    mean = acc / B
+    var = acc2 / B - mean ** 2
+    E = np.outer(r, c) / N
+    V = np.outer(r, c) * np.outer(N - r, N - c) / (N ** 2 * (N - 1))
+    z = (mean - E) / np.sqrt(V / B)
+    assert np.abs(z).max() < 5, np.unravel_index(np.abs(z).argmax(), z.shape)
+    assert np.all(np.abs(var / V - 1) < 0.25)
+
+
+def test_week_pvalue_near_paper():
+    """Section 4.2 reports p = 0.000125 (1255 of 10027008) for Table 2, and
+    0.000127 from stats::fisher.test; 160000 oracle replicates (8 threads)
+    must count 20 +- 4 sqrt(20)."""
+    import threading
+    tab = _golden_table("fisher_week.txt")
+    B, T = 160000, 8
+    rec = O.create_streams(GEN, workloads.random_seed(14), B)
+    counts = []
+
+    def work(lo, hi):
+        cnt, _ = O.fisher_count(GEN, rec[lo:hi].copy(), tab)
+        counts.append(cnt)
+
+    ts = [threading.Thread(target=work, args=(k * B // T, (k + 1) * B // T)) for k in range(T)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    expect = 0.000125 * B
+    assert abs(sum(counts) - expect) < 4 * math.sqrt(expect), sum(counts)
