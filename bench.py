@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
     ap.add_argument("--no-variants", action="store_true", help="skip f32/normal/exponential timings")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--no-tables", action="store_true", help="skip the contingency-table / Fisher timings")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
@@ -197,6 +199,81 @@ def bench_batched(torch, P, workloads, reps=3):
     return res
 
 
+def bench_tables(torch, P, workloads, reps=10):
+    """Section 4 consumer: 1e6 random 2x2..5x5 tables with fixed margins
+    (totals 5..200), one stream each, per launch (HIP events); and fisher.sim
+    on the two tables the paper tests (12 x 12 with B = 2^20, 7 x 12 with
+    B = 10,027,008), one MRG32k3a stream per replicate."""
+    def read_golden(name):
+        with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+            return [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+
+    n = 1_000_000
+    I, J, rows, cols = workloads.contingency_margins(n)
+    c = P.mrg_creator_init(workloads.random_seed())
+    d = P.mrg_streams_create_device(c, n)
+    dI, dJ, dr, dc = [torch.from_numpy(a).cuda() for a in (I, J, rows, cols)]
+    tabs = torch.empty((n, 5, 5), dtype=torch.int32, device="cuda")
+    stats = torch.empty(n, dtype=torch.float64, device="cuda")
+    P.mrg_tables_sample(d, dI, dJ, dr, dc, tables=tabs, stats=stats)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        P.mrg_tables_sample(d, dI, dJ, dr, dc, tables=tabs, stats=stats)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    draws = int(((I - 1) * (J - 1)).sum())
+    res = {"workload": "1e6 tables, shapes 2x2..5x5, margins uniform 5..200, 1 stream per table, "
+                       "int32 tables + statistic",
+           "ms": round(ms, 3), "Mtables_per_s": round(n / ms / 1e3, 1),
+           "GUniforms_per_s": round(draws / ms / 1e6, 2)}
+    del d, tabs, stats
+    fis = {}
+    for name, B, paper_s in (("fisher_month.txt", 1 << 20, 0.348), ("fisher_week.txt", 10027008, 2.030)):
+        tab = np.array([[int(v) for v in r] for r in read_golden(name)], dtype=np.int32)
+        c = P.mrg_creator_init(workloads.random_seed(44))
+        d = P.mrg_streams_create_device(c, B)
+        P.mrg_fisher_sim(d, tab, B=min(B, 4096))
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        cnt, _, _ = P.mrg_fisher_sim(d, tab)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        fis[name.split("_")[1].split(".")[0]] = {
+            "table": f"{tab.shape[0]}x{tab.shape[1]}", "B": B, "ms": round(ms, 2),
+            "Mtables_per_s": round(B / ms / 1e3, 2), "pvalue": round(P.mrg_fisher_pvalue(int(cnt.item()), B), 6),
+            "paper_V100_s": paper_s}
+        del d
+    res["fisher"] = fis
+    return res
+
+
+def bench_serving(torch, P, workloads, rates=(2000, 10000, 50000), duration=1.0):
+    """The request loop: Poisson arrivals from 256 sessions (64 device
+    streams each), lengths log-uniform in [1e2, 1e6] fp64 normals, a 32 GB
+    output pool; continuous batching on 4 HIP streams against one plain
+    launch per request.  Latency = completion - arrival."""
+    pool = torch.empty(32 << 30, dtype=torch.uint8, device="cuda")
+    out = {}
+    for rate in rates:
+        t, sess, lens = workloads.poisson_arrivals(float(rate), duration, rng_seed=rate)
+        row = {}
+        for mode, name in ((0, "batched"), (1, "plain")):
+            srv = P.Server(256, workloads.random_seed(), pool, mode=mode)
+            lat, span = srv.drive((t * 1e9).astype(np.uint64), sess, lens)
+            srv.close()
+            lat_ms = lat / 1e6
+            row[name] = {"GSamples_per_s": round(float(lens.sum()) / (span / 1e9) / 1e9, 3),
+                         "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                         "p99_ms": round(float(np.percentile(lat_ms, 99)), 3)}
+        out[f"{rate}_per_s"] = dict(requests=int(len(t)), **row)
+    del pool
+    return {"workload": f"Poisson arrivals for {duration:g} s, 256 sessions x 64 streams, lengths log-uniform "
+                        "in [1e2, 1e6] fp64 normals, 32 GB pool", "rates": out}
+
+
 def main():
     args = parse()
     if args.pmc_summary:
@@ -307,6 +384,15 @@ def main():
 
     if not args.no_batch:
         res["batched"] = bench_batched(torch, P, workloads)
+        torch.cuda.empty_cache()
+
+    if not args.no_tables:
+        res["tables"] = bench_tables(torch, P, workloads)
+        torch.cuda.empty_cache()
+
+    if not args.no_serving:
+        res["serving"] = bench_serving(torch, P, workloads)
+        torch.cuda.empty_cache()
 
     if args.copy_probe:
         a = torch.empty(COPY_PROBE_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)

@@ -304,7 +304,7 @@ mrg_status mrg_fisher_sim(mrg_generator gen, mrg_stream* dev_streams, uint64_t B
         return fail(MRG_E_INVALID_ARG, "misaligned pointer");
     int32_t r[kFisherMaxDim] = {0}, c[kFisherMaxDim] = {0};
     int64_t total = 0;
-    double stat = 0.0;  // -sum log(n!), row-major, with the host's lgamma
+    double stat = 0.0;  // -sum log(n!), row-major, from the same values as the device table
     for (int i = 0; i < I; ++i)
         for (int j = 0; j < J; ++j) {
             const int32_t v = observed[i * J + j];
@@ -312,7 +312,7 @@ mrg_status mrg_fisher_sim(mrg_generator gen, mrg_stream* dev_streams, uint64_t B
             r[i] += v;
             c[j] += v;
             total += v;
-            stat -= std::lgamma(static_cast<double>(v) + 1.0);
+            stat -= host_log_factorial(v);
         }
     if (total > kTableMaxTotal) return fail(MRG_E_INVALID_ARG, "grand total above 2^20");
     const double threshold = stat / (1.0 + 64.0 * DBL_EPSILON);

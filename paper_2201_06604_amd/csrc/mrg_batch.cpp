@@ -128,7 +128,9 @@ mrg_status build(mrg_batch_plan& P) {
         L.r = static_cast<uint32_t>(q.n % q.n_streams);
         const uint64_t cnt_max = L.q + (L.r ? 1 : 0);
         const uint64_t units = L.dist == kNormal ? (cnt_max + 1) / 2 : cnt_max;
-        const uint64_t chunk = std::min<uint64_t>(units, P.tile_units);
+        uint64_t chunk = std::min<uint64_t>(units, P.tile_units);
+        if (const uint32_t split = P.user[i].split)  // latency: spread a long request over the chip
+            chunk = std::min<uint64_t>(chunk, std::max<uint64_t>(96, (units + split - 1) / split));
         const uint64_t n_chunks = (units + chunk - 1) / chunk;
         L.chunk = static_cast<uint32_t>(chunk);
         L.n_chunks = static_cast<uint32_t>(n_chunks);

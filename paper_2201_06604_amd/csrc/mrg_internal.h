@@ -98,6 +98,8 @@ struct PlanReq {
     mrg_request q;
     uint64_t offset;    // steps each stream advances before its first draw
     int no_writeback;   // 1 = do not write the stream records back
+    uint32_t split;     // > 0: cut each stream block into about this many tiles
+                        // (at least 96 units each), for latency; 0 = tile_units
 };
 
 mrg_status plan_internal(const std::vector<PlanReq>& reqs, uint32_t tile_units, mrg_batch_plan** out);
@@ -120,6 +122,7 @@ constexpr int kFisherMaxDim = 32;
 constexpr int64_t kTableMaxTotal = 1 << 20;  // grand total of one table at most
 hipError_t launch_tables(int gen, uint32_t* streams, uint64_t n, const int32_t* I, const int32_t* J, const int32_t* rows,
                          const int32_t* cols, int32_t* tabs, double* stats, hipStream_t s);
+double host_log_factorial(int64_t k);  // lgamma(k+1) in long double, rounded to double
 hipError_t launch_fisher(int gen, uint32_t* streams, uint64_t B, int I, int J, const int32_t* r, const int32_t* c,
                          double threshold, unsigned long long* count, double* stats, hipStream_t s);
 

@@ -37,6 +37,11 @@ uint64_t steady_ns() {
 
 size_t round256(size_t n) { return (n + 255) / 256 * 256; }
 
+// A served request is cut into about this many tiles per 64-stream block (at
+// least 96 units each), so that a long request runs on many waves at once;
+// the lane workspaces are sized for it.
+constexpr uint32_t kServeSplit = 64;
+
 // First-fit allocator over [0, total) in 256-byte granules; neighbours merge
 // on release.
 struct Pool {
@@ -230,7 +235,7 @@ bool mrg_server::launch_batch(Lane& L) {
         q.dtype = t.dtype;
         q.param = t.param;
         q.out = static_cast<char*>(cfg.pool) + off;
-        reqs.push_back(PlanReq{q, t.offset, 1});
+        reqs.push_back(PlanReq{q, t.offset, 1, kServeSplit});
         ids.push_back(pending.front());
         pending.pop_front();
     }
@@ -399,8 +404,8 @@ mrg_status mrg_server_create(const mrg_server_cfg* cfg, mrg_server** out) {
     if (e == hipSuccess) e = hipDeviceSynchronize();
 
     // lanes: workspace sized for max_batch requests, each cut into at most
-    // 64 chunks of ceil(S/64) stream blocks
-    const size_t max_tiles = static_cast<size_t>(s->cfg.max_batch) * ((S + 63) / 64) * 64;
+    // kServeSplit chunks of ceil(S/64) stream blocks
+    const size_t max_tiles = static_cast<size_t>(s->cfg.max_batch) * ((S + 63) / 64) * kServeSplit;
     const size_t ws_bytes = 256 + round256(s->cfg.max_batch * sizeof(BatchSlot)) +
                             round256(s->cfg.max_batch * sizeof(BatchReq)) + round256(max_tiles * sizeof(BatchTile)) +
                             1024;

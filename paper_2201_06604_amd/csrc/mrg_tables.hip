@@ -11,9 +11,19 @@
 // order.  No FMA contraction (the library is built with -ffp-contract=off),
 // so the integers match bit for bit.
 //
+// pmf(mode)/pmf(lo) can pass 2^1024 (it does for the day-of-week table of
+// Section 4.2), so the weights carry an extended exponent: a weight above
+// 2^600 and the running sum are scaled by 2^-600 (exact), and the search
+// compares u*W with the running sum at W's scale.  The mantissas are those of
+// the same operations on an unbounded exponent range.
+//
 // One lane owns one table.  The loops' trip counts depend on the margins, so
 // lanes of a wave diverge; that is the price of exact inversion.
 #include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <mutex>
+#include <vector>
 
 #include "mrg_engine.h"
 #include "mrg_internal.h"
@@ -26,29 +36,48 @@ __device__ __forceinline__ int hyper_invert(double u, int64_t Np, int64_t K, int
     if (lo < 0) lo = 0;
     const int64_t hi = n < K ? n : K;
     if (hi <= lo) return static_cast<int>(lo);
+    constexpr double kBig = 0x1p600;
+    constexpr int kScaleExp = 600;
     double W = 0.0, w = 1.0;
+    int scales = 0;
     for (int64_t x = lo; x <= hi; ++x) {
         W += w;
         if (x < hi) {
             const double num = static_cast<double>((K - x) * (n - x));
             const double den = static_cast<double>((x + 1) * (Np - K - n + x + 1));
             w = w * num / den;
+            if (w > kBig) {
+                w = ldexp(w, -kScaleExp);
+                W = ldexp(W, -kScaleExp);
+                ++scales;
+            }
         }
     }
     const double target = u * W;
     double s = 0.0;
     w = 1.0;
+    int done = 0;
     for (int64_t x = lo; x <= hi; ++x) {
         s += w;
-        if (target <= s) return static_cast<int>(x);
+        if (target <= ldexp(s, -kScaleExp * (scales - done))) return static_cast<int>(x);
         const double num = static_cast<double>((K - x) * (n - x));
         const double den = static_cast<double>((x + 1) * (Np - K - n + x + 1));
         w = w * num / den;
+        if (w > kBig) {
+            w = ldexp(w, -kScaleExp);
+            s = ldexp(s, -kScaleExp);
+            ++done;
+        }
     }
     return static_cast<int>(hi);
 }
 
-__device__ __forceinline__ double log_factorial(int n) { return lgamma(static_cast<double>(n) + 1.0); }
+// log(n!) for n <= kTableMaxTotal: lgamma(n+1) in long double on the host,
+// rounded to double, uploaded once per device (ensure_logfact).  Every entry
+// of a valid table is at most its grand total, so the index is in range.
+__device__ double g_logfact[kTableMaxTotal + 1];
+
+__device__ __forceinline__ double log_factorial(int n) { return g_logfact[n]; }
 
 // One I x J table (I, J <= MAXD) with row totals r[], column totals c[]:
 // entries to tab[i*ld + j] (when tab is not null); returns -sum log(n_ij!)
@@ -178,8 +207,38 @@ __global__ void __launch_bounds__(256) fisher_kernel(FisherArgs a) {
     atomicAdd(a.count, lane == 0 ? wave_hits : 0ull);
 }
 
+double host_log_factorial(int64_t k) {
+    int sign = 0;
+    return static_cast<double>(lgammal_r(static_cast<long double>(k) + 1.0L, &sign));
+}
+
+// One upload of the log-factorial table per device, before the first table
+// launch there (synchronous; a launch captured in a graph needs one call
+// made beforehand on the device).
+hipError_t ensure_logfact() {
+    static std::mutex mu;
+    static std::vector<char> ready;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    if (static_cast<size_t>(dev) < ready.size() && ready[dev]) return hipSuccess;
+    static std::vector<double> host;
+    if (host.empty()) {
+        host.resize(kTableMaxTotal + 1);
+        for (int64_t k = 0; k <= kTableMaxTotal; ++k)
+            host[k] = host_log_factorial(k);
+    }
+    e = hipMemcpyToSymbol(HIP_SYMBOL(g_logfact), host.data(), host.size() * sizeof(double));
+    if (e != hipSuccess) return e;
+    if (ready.size() <= static_cast<size_t>(dev)) ready.resize(dev + 1, 0);
+    ready[dev] = 1;
+    return hipSuccess;
+}
+
 hipError_t launch_tables(int gen, uint32_t* streams, uint64_t n, const int32_t* I, const int32_t* J,
                          const int32_t* rows, const int32_t* cols, int32_t* tabs, double* stats, hipStream_t s) {
+    if (hipError_t e = ensure_logfact()) return e;
     const dim3 grid(static_cast<unsigned>((n + 255) / 256));
     if (gen == kGen32k3a)
         hipLaunchKernelGGL(tables_kernel<kGen32k3a>, grid, dim3(256), 0, s, streams, n, I, J, rows, cols, tabs, stats);
@@ -202,6 +261,9 @@ hipError_t launch_fisher(int gen, uint32_t* streams, uint64_t B, int I, int J, c
     a.threshold = threshold;
     a.count = count;
     a.stats = stats;
+    if (B) {
+        if (hipError_t e = ensure_logfact()) return e;
+    }
     hipLaunchKernelGGL(fisher_clear_kernel, dim3(1), dim3(1), 0, s, count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || B == 0) return e;
