@@ -23,7 +23,10 @@ S_STREAMS = 262144
 PER_STREAM = 4096
 N = S_STREAMS * PER_STREAM
 HBM_PEAK_GBPS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2201_06604_amd", "csrc", "mrg_kernels.hip")
+# every source the generate kernel is compiled from: counters taken before a
+# change to any of them no longer describe the kernel
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2201_06604_amd", "csrc", f)
+               for f in ("mrg_kernels.hip", "mrg_engine.h", "mrg_math.h", "mrg_internal.h")]
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "gen_kernel_uniform_f64_262144x4096_traffic.json")
 COPY_PROBE_BYTES = 1 << 30
 
@@ -48,8 +51,11 @@ def parse():
 
 def kernel_sha():
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def pmc_summary(fetch_csv, write_csv):

@@ -73,15 +73,24 @@ struct Mat3 {
 };
 
 // x mod (2^B - c) for any 64-bit x, B = 32 or 31, 1 <= c < 2^15.  Each fold
-// maps h*2^B + l to h*c + l; four folds bring any 64-bit value below
-// 2^B + 2c, and one conditional subtraction finishes.
+// maps h*2^B + l to h*c + l.  B = 32: three folds leave x < 2^32 (the bounds
+// below); B = 31: four folds leave x < 2^31.  Then x < 2m and one
+// conditional subtraction finishes.
 template <int B = 32>
 MRG_HD constexpr uint32_t fold64(uint64_t x, uint32_t c) {
     constexpr uint64_t mask = (static_cast<uint64_t>(1) << B) - 1;
-    for (int i = 0; i < 4; ++i) x = (x >> B) * c + (x & mask);
+    if constexpr (B == 32) {
+        x = (x >> 32) * c + (x & mask);  // < 2^47 + 2^32
+        x = (x >> 32) * c + (x & mask);  // < 2^32 + 2^30 + c
+        x = (x >> 32) * c + (x & mask);  // < 2^32
+    } else {
+        x = (x >> 31) * c + (x & mask);  // < 2^48 + 2^31
+        x = (x >> 31) * c + (x & mask);  // < 2^32 + 2^31
+        x = (x >> 31) * c + (x & mask);  // < 2^31 + 2c
+        x = (x >> 31) * c + (x & mask);  // < 2^31
+    }
     const uint64_t m = (static_cast<uint64_t>(1) << B) - c;
-    while (x >= m) x -= m;  // at most twice
-    return static_cast<uint32_t>(x);
+    return static_cast<uint32_t>(x >= m ? x - m : x);
 }
 
 template <int B = 32>
