@@ -134,9 +134,9 @@ mrg_status mrg_streams_create_host(mrg_generator gen, mrg_creator* creator, size
                                    mrg_stream* host_out);
 
 /* createStreamsGpu (Section 2.1): the same n streams written by a kernel to
- * device memory `dev_out` (n records, 4-byte aligned).  Identical records
- * to mrg_streams_create_host; the creator (host value) advances the same
- * way once the launch has been enqueued. */
+ * device memory `dev_out` (n records, 4-byte aligned, n <= 2^36).  Identical
+ * records to mrg_streams_create_host; the creator (host value) advances the
+ * same way once the launch has been enqueued. */
 mrg_status mrg_streams_create_device(mrg_generator gen, mrg_creator* creator, size_t n,
                                      mrg_stream* dev_out, hipStream_t stream);
 

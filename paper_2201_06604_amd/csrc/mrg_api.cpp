@@ -133,7 +133,7 @@ mrg_status mrg_streams_create_device(mrg_generator gen, mrg_creator* creator, si
     if (n == 0) return ok();
     if (!dev_out) return fail(MRG_E_INVALID_ARG, "dev_out is NULL");
     if (reinterpret_cast<uintptr_t>(dev_out) % 4) return fail(MRG_E_INVALID_ARG, "dev_out misaligned");
-    if (n > (static_cast<size_t>(1) << 40)) return fail(MRG_E_INVALID_ARG, "n too large");
+    if (n > (static_cast<size_t>(1) << 36)) return fail(MRG_E_INVALID_ARG, "n above 2^36");
     uint32_t next[6];
     std::memcpy(next, creator->s, sizeof(next));
     host_jump_pow2(gid(gen), next, static_cast<uint64_t>(n), true);

@@ -509,25 +509,46 @@ __global__ void __launch_bounds__(256) batch_finalize_kernel(BatchLaunch B) {
 }
 
 // ------------------------------------------------------ stream creation
-// Stream i = J^i creator with J = A^Z (Z = 2^127, or 2^134 for MRG31k3p):
-// multiply by J^(2^b) for each set bit b of i (the per-bit tables are uniform
-// scalar loads).
+// Stream i = J^i creator with J = A^Z (Z = 2^127, or 2^134 for MRG31k3p),
+// in two passes: create_starts_kernel computes stream 64w (the first stream
+// of each group of 64) from the bits of 64w, and create_lanes_kernel takes
+// stream 64w + l to J^l times it (the 6 low bits).  The long chain of
+// matrix-vector products is done once per 64 streams instead of per stream.
+// The per-bit tables are read with wave-uniform indices (scalar loads).
 template <int G>
-__global__ void __launch_bounds__(256) create_kernel(uint32_t* out, uint64_t n, uint32_t c0, uint32_t c1,
-                                                     uint32_t c2, uint32_t c3, uint32_t c4, uint32_t c5,
-                                                     int nbits) {
-    uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t x[6] = {c0, c1, c2, c3, c4, c5};
-    for (int b = 0; b < nbits; ++b)
-        if ((i >> b) & 1) dev_apply<G>(dev_tab<G>().stream_pow2[0][b], dev_tab<G>().stream_pow2[1][b], x);
-    uint32_t* rec = out + i * 18;
+__device__ __forceinline__ void write_record(uint32_t* rec, const uint32_t x[6]) {
 #pragma unroll
     for (int w = 0; w < 6; ++w) {
         rec[w] = x[w];
         rec[6 + w] = x[w];
         rec[12 + w] = x[w];
     }
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) create_starts_kernel(uint32_t* out, uint64_t n_groups, uint32_t c0,
+                                                            uint32_t c1, uint32_t c2, uint32_t c3, uint32_t c4,
+                                                            uint32_t c5, int nbits) {
+    const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= n_groups) return;
+    uint32_t x[6] = {c0, c1, c2, c3, c4, c5};
+    for (int b = 0; b < nbits; ++b)  // stream index 64 g: bit b of g is bit b + 6
+        if ((g >> b) & 1) dev_apply<G>(dev_tab<G>().stream_pow2[0][b + 6], dev_tab<G>().stream_pow2[1][b + 6], x);
+    write_record<G>(out + g * 64 * 18, x);
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) create_lanes_kernel(uint32_t* out, uint64_t n) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n || (i & 63) == 0) return;  // group starts are already written
+    const uint32_t* first = out + (i & ~static_cast<uint64_t>(63)) * 18;
+    uint32_t x[6];
+#pragma unroll
+    for (int w = 0; w < 6; ++w) x[w] = first[w];
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        if ((i >> b) & 1) dev_apply<G>(dev_tab<G>().stream_pow2[0][b], dev_tab<G>().stream_pow2[1][b], x);
+    write_record<G>(out + i * 18, x);
 }
 
 template <int G>
@@ -585,16 +606,21 @@ static unsigned grid1d(uint64_t n, unsigned block) {
     return static_cast<unsigned>((n + block - 1) / block);
 }
 
-hipError_t launch_create(int gen, uint32_t* out, uint64_t n, const uint32_t c[6], hipStream_t s) {
-    int nbits = 0;
-    while (nbits < 64 && ((n - 1) >> nbits)) ++nbits;
-    if (gen == kGen32k3a)
-        hipLaunchKernelGGL(create_kernel<kGen32k3a>, dim3(grid1d(n, 256)), dim3(256), 0, s, out, n, c[0], c[1],
-                           c[2], c[3], c[4], c[5], nbits);
-    else
-        hipLaunchKernelGGL(create_kernel<kGen31k3p>, dim3(grid1d(n, 256)), dim3(256), 0, s, out, n, c[0], c[1],
-                           c[2], c[3], c[4], c[5], nbits);
+template <int G>
+static hipError_t launch_create_t(uint32_t* out, uint64_t n, const uint32_t c[6], hipStream_t s) {
+    const uint64_t groups = (n + 63) / 64;
+    int nbits = 0;  // bits of the largest group index
+    while (nbits < 58 && ((groups - 1) >> nbits)) ++nbits;
+    hipLaunchKernelGGL(create_starts_kernel<G>, dim3(grid1d(groups, 256)), dim3(256), 0, s, out, groups, c[0], c[1],
+                       c[2], c[3], c[4], c[5], nbits);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n == 1) return e;
+    hipLaunchKernelGGL(create_lanes_kernel<G>, dim3(grid1d(n, 256)), dim3(256), 0, s, out, n);
     return hipGetLastError();
+}
+
+hipError_t launch_create(int gen, uint32_t* out, uint64_t n, const uint32_t c[6], hipStream_t s) {
+    return gen == kGen32k3a ? launch_create_t<kGen32k3a>(out, n, c, s) : launch_create_t<kGen31k3p>(out, n, c, s);
 }
 
 hipError_t launch_reset(int gen, uint32_t* streams, uint64_t n, int kind, hipStream_t s) {

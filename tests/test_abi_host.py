@@ -363,3 +363,11 @@ def test_generate_paper_validation():
     assert st(4, 2, 4, 4, 2, 2, out=ctypes.c_void_p(4100)) == -1
     assert st(4, 2, 4, 4, 2, 2, gen=5) == -1
     assert st(4, 0, 4, 4, 2, 2, out=None) == 0  # empty block: no-op
+
+
+def test_device_creation_size_limit():
+    c = P.mrg_creator_init([12345] * 6)
+    before = P.creator_words(c).copy()
+    st = P.lib().mrg_streams_create_device(1, ctypes.byref(c), (1 << 36) + 1, ctypes.c_void_p(4096), None)
+    assert st == -1
+    np.testing.assert_array_equal(P.creator_words(c), before)
