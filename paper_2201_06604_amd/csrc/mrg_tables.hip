@@ -3,19 +3,9 @@
 // table, entries drawn in row-major order by inversion of their conditional
 // hypergeometric distributions, one uniform per free entry.
 //
-// Inversion (identical operations to the definition used for parity): entry
-// (i, j) given the entries before it takes x in [lo, hi] with weights
-// w(lo) = 1, w(x+1) = w(x) * ((K-x)(n-x)) / ((x+1)(N'-K-n+x+1)) in double
-// precision (exact integer products, one rounded multiply, one rounded
-// divide); the entry is the smallest x with u*W <= w(lo)+...+w(x), sums in
-// order.  No FMA contraction (the library is built with -ffp-contract=off),
-// so the integers match bit for bit.
-//
-// pmf(mode)/pmf(lo) can pass 2^1024 (it does for the day-of-week table of
-// Section 4.2), so the weights carry an extended exponent: a weight above
-// 2^600 and the running sum are scaled by 2^-600 (exact), and the search
-// compares u*W with the running sum at W's scale.  The mantissas are those of
-// the same operations on an unbounded exponent range.
+// Each entry is sampled by hyper_invert_ck (mrg_hyper.h): the inversion that
+// the oracle defines, with two shortcuts that give the same bits; the
+// checkpoints of its search live in LDS, 8 per lane.
 //
 // One lane owns one table.  The loops' trip counts depend on the margins, so
 // lanes of a wave diverge; that is the price of exact inversion.
@@ -26,51 +16,14 @@
 #include <vector>
 
 #include "mrg_engine.h"
+#include "mrg_hyper.h"
 #include "mrg_internal.h"
 #include "mrg_math.h"
 
 namespace mrg355 {
 
-__device__ __forceinline__ int hyper_invert(double u, int64_t Np, int64_t K, int64_t n) {
-    int64_t lo = n - (Np - K);
-    if (lo < 0) lo = 0;
-    const int64_t hi = n < K ? n : K;
-    if (hi <= lo) return static_cast<int>(lo);
-    constexpr double kBig = 0x1p600;
-    constexpr int kScaleExp = 600;
-    double W = 0.0, w = 1.0;
-    int scales = 0;
-    for (int64_t x = lo; x <= hi; ++x) {
-        W += w;
-        if (x < hi) {
-            const double num = static_cast<double>((K - x) * (n - x));
-            const double den = static_cast<double>((x + 1) * (Np - K - n + x + 1));
-            w = w * num / den;
-            if (w > kBig) {
-                w = ldexp(w, -kScaleExp);
-                W = ldexp(W, -kScaleExp);
-                ++scales;
-            }
-        }
-    }
-    const double target = u * W;
-    double s = 0.0;
-    w = 1.0;
-    int done = 0;
-    for (int64_t x = lo; x <= hi; ++x) {
-        s += w;
-        if (target <= ldexp(s, -kScaleExp * (scales - done))) return static_cast<int>(x);
-        const double num = static_cast<double>((K - x) * (n - x));
-        const double den = static_cast<double>((x + 1) * (Np - K - n + x + 1));
-        w = w * num / den;
-        if (w > kBig) {
-            w = ldexp(w, -kScaleExp);
-            s = ldexp(s, -kScaleExp);
-            ++done;
-        }
-    }
-    return static_cast<int>(hi);
-}
+constexpr int kCk = 8;         // inversion checkpoints per lane (LDS)
+constexpr int kTableBlock = 256;
 
 // log(n!) for n <= kTableMaxTotal: lgamma(n+1) in long double on the host,
 // rounded to double, uploaded once per device (ensure_logfact).  Every entry
@@ -84,7 +37,7 @@ __device__ __forceinline__ double log_factorial(int n) { return g_logfact[n]; }
 // summed row-major.  The engine advances (I-1)(J-1) steps.
 template <int MAXD, typename Engine>
 __device__ double sample_table(Engine& e, double norm, int I, int J, const int32_t* r, const int32_t* c, int32_t* tab,
-                               int ld) {
+                               int ld, HyperCk ck) {
     int32_t crem[MAXD];
     for (int j = 0; j < J; ++j) crem[j] = c[j];
     double stat = 0.0;
@@ -94,7 +47,7 @@ __device__ double sample_table(Engine& e, double norm, int I, int J, const int32
         for (int j = 0; j < J; ++j) Np += crem[j];
         for (int j = 0; j < J - 1; ++j) {
             const double u = to_f64(e.step_rot()) * norm;
-            const int x = hyper_invert(u, Np, crem[j], rrem);
+            const int x = hyper_invert_ck<kCk>(u, Np, crem[j], rrem, ck);
             if (tab) tab[i * ld + j] = x;
             stat -= log_factorial(x);
             rrem -= x;
@@ -130,9 +83,12 @@ struct GenOf<kGen31k3p> {
 // in total or total more than kTableMaxTotal gets zeros and a NaN statistic,
 // and its stream is left as it was (the checks also bound every loop).
 template <int G>
-__global__ void __launch_bounds__(256) tables_kernel(uint32_t* streams, uint64_t n, const int32_t* I,
-                                                     const int32_t* J, const int32_t* rows, const int32_t* cols,
-                                                     int32_t* tabs, double* stats) {
+__global__ void __launch_bounds__(kTableBlock) tables_kernel(uint32_t* streams, uint64_t n, const int32_t* I,
+                                                             const int32_t* J, const int32_t* rows, const int32_t* cols,
+                                                             int32_t* tabs, double* stats) {
+    __shared__ double ck_s[kCk * kTableBlock], ck_w[kCk * kTableBlock];
+    __shared__ int ck_r[kCk * kTableBlock];
+    const HyperCk ck{ck_s + threadIdx.x, ck_w + threadIdx.x, ck_r + threadIdx.x, kTableBlock};
     const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= n) return;
     int32_t* out = tabs + t * 25;
@@ -160,7 +116,7 @@ __global__ void __launch_bounds__(256) tables_kernel(uint32_t* streams, uint64_t
     for (int w = 0; w < 6; ++w) x[w] = rec[w];
     typename GenOf<G>::Engine e;
     e.load(x);
-    const double stat = sample_table<5>(e, GenOf<G>::norm, It, Jt, rows + t * 5, cols + t * 5, out, 5);
+    const double stat = sample_table<5>(e, GenOf<G>::norm, It, Jt, rows + t * 5, cols + t * 5, out, 5, ck);
     if (stats) stats[t] = stat;
     e.save(x);
 #pragma unroll
@@ -185,7 +141,10 @@ struct FisherArgs {
 // replicates whose statistic is <= threshold (one atomic per wave; every
 // lane executes it, with the wave's count on lane 0 and 0 elsewhere).
 template <int G>
-__global__ void __launch_bounds__(256) fisher_kernel(FisherArgs a) {
+__global__ void __launch_bounds__(kTableBlock) fisher_kernel(FisherArgs a) {
+    __shared__ double ck_s[kCk * kTableBlock], ck_w[kCk * kTableBlock];
+    __shared__ int ck_r[kCk * kTableBlock];
+    const HyperCk ck{ck_s + threadIdx.x, ck_w + threadIdx.x, ck_r + threadIdx.x, kTableBlock};
     const uint64_t b = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint32_t lane = threadIdx.x & 63;
     bool hit = false;
@@ -196,7 +155,7 @@ __global__ void __launch_bounds__(256) fisher_kernel(FisherArgs a) {
         for (int w = 0; w < 6; ++w) x[w] = rec[w];
         typename GenOf<G>::Engine e;
         e.load(x);
-        const double stat = sample_table<kFisherMaxDim>(e, GenOf<G>::norm, a.I, a.J, a.r, a.c, nullptr, 0);
+        const double stat = sample_table<kFisherMaxDim>(e, GenOf<G>::norm, a.I, a.J, a.r, a.c, nullptr, 0, ck);
         hit = stat <= a.threshold;
         if (a.stats) a.stats[b] = stat;
         e.save(x);
@@ -239,11 +198,13 @@ hipError_t ensure_logfact() {
 hipError_t launch_tables(int gen, uint32_t* streams, uint64_t n, const int32_t* I, const int32_t* J,
                          const int32_t* rows, const int32_t* cols, int32_t* tabs, double* stats, hipStream_t s) {
     if (hipError_t e = ensure_logfact()) return e;
-    const dim3 grid(static_cast<unsigned>((n + 255) / 256));
+    const dim3 grid(static_cast<unsigned>((n + kTableBlock - 1) / kTableBlock));
     if (gen == kGen32k3a)
-        hipLaunchKernelGGL(tables_kernel<kGen32k3a>, grid, dim3(256), 0, s, streams, n, I, J, rows, cols, tabs, stats);
+        hipLaunchKernelGGL(tables_kernel<kGen32k3a>, grid, dim3(kTableBlock), 0, s, streams, n, I, J, rows, cols, tabs,
+                           stats);
     else
-        hipLaunchKernelGGL(tables_kernel<kGen31k3p>, grid, dim3(256), 0, s, streams, n, I, J, rows, cols, tabs, stats);
+        hipLaunchKernelGGL(tables_kernel<kGen31k3p>, grid, dim3(kTableBlock), 0, s, streams, n, I, J, rows, cols, tabs,
+                           stats);
     return hipGetLastError();
 }
 
@@ -267,9 +228,9 @@ hipError_t launch_fisher(int gen, uint32_t* streams, uint64_t B, int I, int J, c
     hipLaunchKernelGGL(fisher_clear_kernel, dim3(1), dim3(1), 0, s, count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || B == 0) return e;
-    const dim3 grid(static_cast<unsigned>((B + 255) / 256));
-    if (gen == kGen32k3a) hipLaunchKernelGGL(fisher_kernel<kGen32k3a>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(fisher_kernel<kGen31k3p>, grid, dim3(256), 0, s, a);
+    const dim3 grid(static_cast<unsigned>((B + kTableBlock - 1) / kTableBlock));
+    if (gen == kGen32k3a) hipLaunchKernelGGL(fisher_kernel<kGen32k3a>, grid, dim3(kTableBlock), 0, s, a);
+    else hipLaunchKernelGGL(fisher_kernel<kGen31k3p>, grid, dim3(kTableBlock), 0, s, a);
     return hipGetLastError();
 }
 
