@@ -537,18 +537,29 @@ __global__ void __launch_bounds__(256) create_starts_kernel(uint32_t* out, uint6
     write_record<G>(out + g * 64 * 18, x);
 }
 
+// The block's 256 records (18 KiB, contiguous in memory) are assembled in LDS
+// and written with coalesced dword stores: written lane by lane, each store
+// instruction would touch 64 lines 72 bytes apart.
 template <int G>
 __global__ void __launch_bounds__(256) create_lanes_kernel(uint32_t* out, uint64_t n) {
-    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n || (i & 63) == 0) return;  // group starts are already written
-    const uint32_t* first = out + (i & ~static_cast<uint64_t>(63)) * 18;
-    uint32_t x[6];
+    __shared__ uint32_t recs[256 * 18];
+    const uint64_t first_i = static_cast<uint64_t>(blockIdx.x) * 256;
+    const uint64_t i = first_i + threadIdx.x;
+    if (i < n) {
+        const uint32_t* start = out + (i & ~static_cast<uint64_t>(63)) * 18;  // written by create_starts_kernel
+        uint32_t x[6];
 #pragma unroll
-    for (int w = 0; w < 6; ++w) x[w] = first[w];
+        for (int w = 0; w < 6; ++w) x[w] = start[w];
 #pragma unroll
-    for (int b = 0; b < 6; ++b)
-        if ((i >> b) & 1) dev_apply<G>(dev_tab<G>().stream_pow2[0][b], dev_tab<G>().stream_pow2[1][b], x);
-    write_record<G>(out + i * 18, x);
+        for (int b = 0; b < 6; ++b)
+            if ((i >> b) & 1) dev_apply<G>(dev_tab<G>().stream_pow2[0][b], dev_tab<G>().stream_pow2[1][b], x);
+        write_record<G>(recs + threadIdx.x * 18, x);
+    }
+    __syncthreads();  // every group start of this block has been read
+    const uint64_t n_here = n - first_i < 256 ? n - first_i : 256;
+    const uint32_t words = static_cast<uint32_t>(n_here) * 18;
+    uint32_t* dst = out + first_i * 18;
+    for (uint32_t k = threadIdx.x; k < words; k += 256) dst[k] = recs[k];
 }
 
 template <int G>
