@@ -6,7 +6,7 @@ stream, element k*S + s = draw k of stream s) + the state write-back.
 Inputs and outputs stay in HBM.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--copy-probe]
-    python bench.py --pmc-summary FETCH_CSV WRITE_CSV
+    python bench.py --pmc-summary FETCH_CSV WRITE_CSV BENCH_LOG
 """
 import argparse
 import json
@@ -43,9 +43,10 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_LOG"), default=None,
                     help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of a "
-                         "--copy-probe run into the traffic summary under profiles/, then exit")
+                         "--copy-probe run into the traffic summary under profiles/, then exit; the "
+                         "kernel-source hash is read from the profiled run's own JSON line in BENCH_LOG")
     return ap.parse_args()
 
 
@@ -58,7 +59,7 @@ def kernel_sha():
     return h.hexdigest()
 
 
-def pmc_summary(fetch_csv, write_csv):
+def pmc_summary(fetch_csv, write_csv, bench_log):
     """HBM bytes per launch of the fp64-uniform generate kernel from the
     FETCH_SIZE and WRITE_SIZE counters (KiB per dispatch), each scaled by what
     the same counter reads for the 1 GiB copy of --copy-probe."""
@@ -73,6 +74,13 @@ def pmc_summary(fetch_csv, write_csv):
         return {k: sum(v) / len(v) for k, v in acc.items()}
 
     fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    sha = None
+    with open(bench_log) as f:
+        for line in f:
+            if line.startswith("{"):
+                sha = json.loads(line)["roofline"].get("source_sha256")
+    if not sha:
+        sys.exit("no kernel-source hash in " + bench_log)
 
     def pick(d, pred):
         ks = [k for k in d if pred(k)]
@@ -91,7 +99,7 @@ def pmc_summary(fetch_csv, write_csv):
            "fetch_kib": g_f, "write_kib": g_w, "copy_fetch_kib": c_f, "copy_write_kib": c_w,
            "fetch_factor": f_fac, "write_factor": w_fac,
            "bytes_per_launch": (g_f * f_fac + g_w * w_fac) * 1024.0,
-           "source_sha256": kernel_sha()}
+           "source_sha256": sha}
     with open(TRAFFIC_JSON, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
@@ -355,7 +363,7 @@ def main():
                      "traffic": None if traffic is None else round(traffic / 1e9, 4),
                      "traffic_unit": "GB per launch",
                      "kernel": "gen_kernel<uniform,f64>", "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_ms": round(gen_avg_ms, 4)},
+                     "avg_launch_ms": round(gen_avg_ms, 4), "source_sha256": kernel_sha()},
     }
 
     # store-only ceiling: torch's fill of the same 8 GiB buffer
