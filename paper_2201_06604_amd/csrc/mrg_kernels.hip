@@ -525,24 +525,41 @@ __device__ __forceinline__ void write_record(uint32_t* rec, const uint32_t x[6])
     }
 }
 
+// Copy jump matrices [first, first + count) of both components into LDS
+// (one burst of independent loads per block instead of a scalar load per
+// step of a lane's serial chain).
+template <int G>
+__device__ __forceinline__ void stage_stream_tables(Mat3 (*dst)[2], int first, int count) {
+    const uint32_t* src0 = dev_tab<G>().stream_pow2[0][first].a;
+    const uint32_t* src1 = dev_tab<G>().stream_pow2[1][first].a;
+    for (int k = threadIdx.x; k < count * 9; k += blockDim.x) {
+        dst[k / 9][0].a[k % 9] = src0[k];
+        dst[k / 9][1].a[k % 9] = src1[k];
+    }
+    __syncthreads();
+}
+
 template <int G>
 __global__ void __launch_bounds__(256) create_starts_kernel(uint32_t* out, uint64_t n_groups, uint32_t c0,
                                                             uint32_t c1, uint32_t c2, uint32_t c3, uint32_t c4,
                                                             uint32_t c5, int nbits) {
+    __shared__ Mat3 tab[58][2];  // J^(2^(b+6)), b < nbits <= 58
+    stage_stream_tables<G>(tab, 6, nbits);
     const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= n_groups) return;
     uint32_t x[6] = {c0, c1, c2, c3, c4, c5};
     for (int b = 0; b < nbits; ++b)  // stream index 64 g: bit b of g is bit b + 6
-        if ((g >> b) & 1) dev_apply<G>(dev_tab<G>().stream_pow2[0][b + 6], dev_tab<G>().stream_pow2[1][b + 6], x);
+        if ((g >> b) & 1) dev_apply<G>(tab[b][0], tab[b][1], x);
     write_record<G>(out + g * 64 * 18, x);
 }
 
 // The block's 256 records (18 KiB, contiguous in memory) are assembled in LDS
-// and written with coalesced dword stores: written lane by lane, each store
-// instruction would touch 64 lines 72 bytes apart.
+// and written with coalesced dword stores.
 template <int G>
 __global__ void __launch_bounds__(256) create_lanes_kernel(uint32_t* out, uint64_t n) {
+    __shared__ Mat3 tab[6][2];  // J^(2^b), b < 6
     __shared__ uint32_t recs[256 * 18];
+    stage_stream_tables<G>(tab, 0, 6);
     const uint64_t first_i = static_cast<uint64_t>(blockIdx.x) * 256;
     const uint64_t i = first_i + threadIdx.x;
     if (i < n) {
@@ -552,7 +569,7 @@ __global__ void __launch_bounds__(256) create_lanes_kernel(uint32_t* out, uint64
         for (int w = 0; w < 6; ++w) x[w] = start[w];
 #pragma unroll
         for (int b = 0; b < 6; ++b)
-            if ((i >> b) & 1) dev_apply<G>(dev_tab<G>().stream_pow2[0][b], dev_tab<G>().stream_pow2[1][b], x);
+            if ((i >> b) & 1) dev_apply<G>(tab[b][0], tab[b][1], x);
         write_record<G>(recs + threadIdx.x * 18, x);
     }
     __syncthreads();  // every group start of this block has been read
