@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--no-tables", action="store_true", help="skip the contingency-table / Fisher timings")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the MRG31k3p and paper-geometry (rnormGpu example) timings")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_LOG"), default=None,
@@ -264,6 +266,38 @@ def bench_tables(torch, P, workloads, reps=10):
     return res
 
 
+def bench_paper(torch, P, workloads, out, reps=5):
+    """The paper's own generator and geometry: MRG31k3p fp64 uniforms at the
+    throughput size (262,144 streams x 4,096, default launch), and the
+    rnormGpu example of Section 3.1 (10^4 x 10^4 fp64 normals from 65,536
+    MRG31k3p streams on a 512 x 128 work-item lattice, Listing 2 placement)."""
+    G = P.MRG_GEN_MRG31K3P
+    c = P.mrg_creator_init(workloads.PAPER_SEED, gen=G)
+    st = P.mrg_streams_create_device(c, S_STREAMS, gen=G)
+
+    def timed(fn):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms = timed(lambda: P.mrg_generate(st, N, P.MRG_UNIFORM, P.MRG_F64, out=out, gen=G))
+    res = {"mrg31k3p_uniform_f64": {"GSamples_per_s": round(N / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4),
+                                    "GB_per_s": round((N * 8 + S_STREAMS * 48) / (ms * 1e-3) / 1e9, 1)}}
+    del st
+    c = P.mrg_creator_init(workloads.PAPER_SEED, gen=G)
+    st = P.mrg_streams_create_device(c, 65536, gen=G)
+    view = out[:10000 * 10000].view(10000, 10000)
+    ms = timed(lambda: P.mrg_generate_paper(st, 10000, 10000, 512, 128, P.MRG_NORMAL, P.MRG_F64, out=view, gen=G))
+    res["rnormGpu_10000x10000_512x128"] = {"ms": round(ms, 3), "GSamples_per_s": round(1e8 / (ms * 1e-3) / 1e9, 1),
+                                           "paper_s": 0.051}
+    return res
+
+
 def bench_serving(torch, P, workloads, rates=(2000, 10000, 50000), duration=1.0):
     """The request loop: Poisson arrivals from 256 sessions (64 device
     streams each), lengths log-uniform in [1e2, 1e6] fp64 normals, a 32 GB
@@ -407,6 +441,9 @@ def main():
     if not args.no_serving:
         res["serving"] = bench_serving(torch, P, workloads)
         torch.cuda.empty_cache()
+
+    if not args.no_paper:
+        res["paper_generator_geometry"] = bench_paper(torch, P, workloads, out)
 
     if args.copy_probe:
         a = torch.empty(COPY_PROBE_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)

@@ -209,3 +209,41 @@ def test_fisher_week_pvalue_near_paper():
     cnt, _, _ = P.mrg_fisher_sim(d, tab)
     k = int(cnt.item())
     assert abs(k - 1255) < 4 * np.sqrt(1255), k
+
+
+def test_tables_and_fisher_replayed_from_a_graph():
+    """Both calls captured in one HIP graph (after a first eager call on the
+    device) and replayed three times with eager work in between: every replay
+    equals the oracle's next call on the same streams."""
+    tab = _golden_table("fisher_month.txt")
+    B, n = 3000, 2000
+    I, J, rows, cols = workloads.contingency_margins(n, rng_seed=51)
+    rec_f = _records(workloads.random_seed(52), B)
+    rec_t = _records(workloads.random_seed(53), n)
+    df, dt = _device(rec_f.view(np.int32).copy()), _device(rec_t.view(np.int32).copy())
+    dI, dJ, dr, dc = _device(I), _device(J), _device(rows), _device(cols)
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    tabs = torch.empty((n, 5, 5), dtype=torch.int32, device="cuda")
+    stats = torch.empty(n, dtype=torch.float64, device="cuda")
+    warm = _device(rec_f[:8].view(np.int32).copy())
+    P.mrg_fisher_sim(warm, tab, B=8)  # first call on the device: table upload
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        P.mrg_fisher_sim(df, tab, count=count)
+        P.mrg_tables_sample(dt, dI, dJ, dr, dc, tables=tabs, stats=stats)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(P.as_u32(df), rec_f)  # capture ran nothing
+    wf, wt = rec_f.copy(), rec_t.copy()
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        wcnt, _ = O.fisher_count(GEN, wf, tab)
+        wtabs, wstats = O.tables(GEN, wt, I, J, rows, cols)
+        assert int(count.item()) == wcnt, rep
+        np.testing.assert_array_equal(tabs.cpu().numpy(), wtabs)
+        _check_stats(stats.cpu().numpy(), wstats)
+        np.testing.assert_array_equal(P.as_u32(df), wf)
+        np.testing.assert_array_equal(P.as_u32(dt), wt)
+        torch.ones(1 << 20, device="cuda").sum().item()  # eager work between replays
+    del g
