@@ -317,9 +317,15 @@ bool mrg_server::launch_plain() {
     return true;
 }
 
+// After any activity the scheduler keeps polling (yielding its core) for
+// this long before it sleeps on the condition variable: a request that
+// arrives within the window is picked up without a thread wake-up.
+constexpr uint64_t kSpinWindowNs = 2000000;
+
 void mrg_server::loop() {
     (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
+    uint64_t last_active = steady_ns();
     while (!stop.load()) {
         bool progress = cfg.mode == 0 ? poll_lanes() : poll_plain();
         if (error == MRG_OK) {
@@ -334,10 +340,11 @@ void mrg_server::loop() {
         st.pool_peak = pool.peak;
         if (progress) {
             cv.notify_all();
+            last_active = steady_ns();
             continue;
         }
-        if (in_flight) {  // something on the device: look again soon
-            lk.unlock();
+        if (in_flight || !pending.empty() || steady_ns() - last_active < kSpinWindowNs) {
+            lk.unlock();  // something on the device or recently active: look again soon
             std::this_thread::yield();
             lk.lock();
         } else {
@@ -580,9 +587,17 @@ mrg_status mrg_server_drive(mrg_server* s, size_t n, const uint64_t* t_arrival_n
             ++finished;
         }
         if (finished < n) {
-            const uint64_t wake = next < n ? t0 + t_arrival_ns[next] : steady_ns() + 200000;
+            // Sleep (woken early by completions) while the next arrival is far
+            // off; within 300 us of it, poll, so that requests are submitted
+            // on time rather than a timer slack late.
             const uint64_t now2 = steady_ns();
-            if (wake > now2) s->cv.wait_for(lk, std::chrono::nanoseconds(std::min<uint64_t>(wake - now2, 200000)));
+            const uint64_t wake = next < n ? t0 + t_arrival_ns[next] : now2 + 200000;
+            if (wake > now2 + 300000) {
+                s->cv.wait_for(lk, std::chrono::nanoseconds(std::min<uint64_t>(wake - now2 - 300000, 200000)));
+            } else {
+                lk.unlock();
+                std::this_thread::yield();
+            }
         }
     }
     {
