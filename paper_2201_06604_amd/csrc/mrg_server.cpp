@@ -110,6 +110,7 @@ struct Lane {
     char* staging = nullptr;          // pinned copy source of the plan tables
     hipEvent_t done_ev = nullptr;
     bool busy = false;
+    bool single = false;              // the lane runs one request as a plain launch
     std::vector<uint64_t> tickets;
     size_t remaining = 0;
     mrg_batch_plan* plan = nullptr;
@@ -171,6 +172,20 @@ bool mrg_server::poll_lanes() {
     bool progress = false;
     for (Lane& L : lanes) {
         if (!L.busy) continue;
+        if (L.single) {  // one plain launch: its event is the completion
+            hipError_t e = hipEventQuery(L.done_ev);
+            if (e == hipSuccess) {
+                auto it = tickets.find(L.tickets[0]);
+                if (it != tickets.end() && it->second.state == kInFlight) complete(L.tickets[0], it->second);
+                L.busy = L.single = false;
+                L.remaining = 0;
+                L.tickets.clear();
+                progress = true;
+            } else if (e != hipErrorNotReady) {
+                fail_hip(e, "plain completion");
+            }
+            continue;
+        }
         for (size_t i = 0; i < L.tickets.size() && L.remaining; ++i) {
             auto it = tickets.find(L.tickets[i]);
             if (it == tickets.end() || it->second.state != kInFlight) continue;
@@ -240,6 +255,35 @@ bool mrg_server::launch_batch(Lane& L) {
         pending.pop_front();
     }
     if (ids.empty()) return false;
+    if (ids.size() == 1) {  // nothing to batch with: one plain launch, no plan upload
+        GenLaunch G{};
+        G.streams = reinterpret_cast<uint32_t*>(reqs[0].q.streams);
+        G.out = reqs[0].q.out;
+        G.S = reqs[0].q.n_streams;
+        G.q = reqs[0].q.n / G.S;
+        G.r = static_cast<uint32_t>(reqs[0].q.n % G.S);
+        G.dist = static_cast<int>(reqs[0].q.dist);
+        G.dtype = static_cast<int>(reqs[0].q.dtype);
+        G.param = reqs[0].q.dist == MRG_EXPONENTIAL ? 1.0 / reqs[0].q.param : 1.0;
+        G.offset = reqs[0].offset;
+        G.no_writeback = 1;
+        plan_generate(G);
+        hipError_t e = launch_generate(G, L.stream);
+        if (e == hipSuccess) e = hipEventRecord(L.done_ev, L.stream);
+        if (e != hipSuccess) {
+            fail_hip(e, "single launch");
+            return false;
+        }
+        L.single = true;
+        L.tickets = ids;
+        L.remaining = 1;
+        L.busy = true;
+        tickets.at(ids[0]).state = kInFlight;
+        in_flight += 1;
+        st.max_in_flight = std::max<uint64_t>(st.max_in_flight, in_flight);
+        ++st.launches;
+        return true;
+    }
     mrg_batch_plan* plan = nullptr;
     for (uint32_t tu = cfg.tile_units;; tu *= 2) {  // coarser tiles until the plan fits the lane
         if (plan_internal(reqs, tu, &plan)) {
