@@ -197,6 +197,49 @@ struct F64Engine {
 };
 
 // ------------------------------------------------------------- transforms
+// log(u) for the generators' uniforms, u in [2^-33, 1): never zero,
+// subnormal, negative or non-finite, so no special cases.  u = m 2^k with m
+// in [sqrt(1/2), sqrt(2)); f = m - 1 (exact); s = f / (2 + f); log(m) =
+// 2 atanh(s) = 2s + 2s (s^2/3 + s^4/5 + ... + s^18/19) (|s| <= 0.1716, so the
+// next term is below 2^-55 relative); log(u) = k ln2 + log(m) with ln2 split
+// so that k * ln2_hi is exact.  The quotient uses a reciprocal refined by two
+// Newton steps and one residual correction.  Accuracy is checked against the
+// library log over every uniform the generators can produce.
+__device__ __forceinline__ double log_unit(double u) {
+    int k = __builtin_amdgcn_frexp_exp(u);          // u = mant * 2^k, mant in [1/2, 1)
+    double m = __builtin_amdgcn_frexp_mant(u);
+    if (m < 0.70710678118654752440) {
+        m = m + m;
+        k -= 1;
+    }
+    const double f = m - 1.0;
+    const double d = 2.0 + f;
+    double y = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, y, 1.0);
+    y = __builtin_fma(e, y, y);
+    e = __builtin_fma(-d, y, 1.0);
+    y = __builtin_fma(e, y, y);
+    double q = f * y;
+    q = __builtin_fma(__builtin_fma(-q, d, f), y, q);  // s = f / d
+    const double z = q * q;
+    double r = 1.0 / 19.0;
+    r = __builtin_fma(r, z, 1.0 / 17.0);
+    r = __builtin_fma(r, z, 1.0 / 15.0);
+    r = __builtin_fma(r, z, 1.0 / 13.0);
+    r = __builtin_fma(r, z, 1.0 / 11.0);
+    r = __builtin_fma(r, z, 1.0 / 9.0);
+    r = __builtin_fma(r, z, 1.0 / 7.0);
+    r = __builtin_fma(r, z, 1.0 / 5.0);
+    r = __builtin_fma(r, z, 1.0 / 3.0);
+    r = r * z;
+    const double s2 = q + q;
+    const double log_m = __builtin_fma(s2, r, s2);
+    const double kd = static_cast<double>(k);
+    constexpr double kLn2Hi = 6.93147180369123816490e-01;  // ln 2 to 32 bits: k * hi exact for |k| < 2^20
+    constexpr double kLn2Lo = 1.90821492927058770002e-10;  // ln 2 - hi
+    return __builtin_fma(kd, kLn2Hi, __builtin_fma(kd, kLn2Lo, log_m));
+}
+
 __device__ __forceinline__ double to_f64(uint32_t z) { return static_cast<double>(z); }
 __device__ __forceinline__ double to_f64(double z) { return z; }
 __device__ __forceinline__ uint32_t to_u32(uint32_t z) { return z; }
