@@ -672,7 +672,8 @@ hipError_t launch_advance(int gen, uint32_t* streams, uint64_t n, uint64_t steps
 //   f64 uniforms   2 streams/lane (16-byte stores), ~2 waves per SIMD, each
 //                  stream whole in one work-item, 256 threads, XCD remap
 //   f32/u32        4 streams/lane, ~4 waves per SIMD, 512 threads, no remap
-//   normal, exp.   VALU-bound: 1 stream/lane, ~16 waves per SIMD
+//   exponential    2 streams/lane, ~4 waves per SIMD (4 chunks per stream)
+//   normal         2 streams/lane, ~8 waves per SIMD (flat from 2 to 16)
 // Non-temporal stores throughout.  Chunks hold at least 96 units; at most
 // 65535 chunks.  A narrower store is used when n_streams or the output
 // alignment does not allow the wide one.
@@ -681,7 +682,8 @@ void plan_generate(GenLaunch& L) {
     const bool plain = L.dist == kUniform || L.dist == kRaw;
     const bool cfg_given = L.block || L.chunk || L.spl || (L.arith && L.arith != kArith31);
     if (!L.arith) L.arith = kArithF64;
-    if (!L.spl) L.spl = plain ? 16 / esz : 1;
+    const bool spl_auto = !L.spl;
+    if (!L.spl) L.spl = plain ? 16 / esz : 2;
     if (!L.block) L.block = (plain && esz == 4) ? 512 : 256;
     if (!cfg_given) {
         L.nontemporal = 1;
@@ -690,12 +692,14 @@ void plan_generate(GenLaunch& L) {
     // at most 16 bytes per store; narrower when the shape does not allow it
     while (L.spl * esz > 16) L.spl /= 2;
     while (L.spl > 1 && (L.S % L.spl || reinterpret_cast<uintptr_t>(L.out) % (L.spl * esz))) L.spl /= 2;
+    if (spl_auto)  // fewer streams than a wave would cover: lanes would idle
+        while (L.spl > 1 && 64ull * L.spl > L.S) L.spl /= 2;
     const uint64_t cnt_max = L.q + (L.r ? 1 : 0);
     const uint64_t units_max = L.dist == kNormal ? (cnt_max + 1) / 2 : cnt_max;
     const uint64_t ws = 64ull * L.spl;
     const uint64_t n_sblk = (static_cast<uint64_t>(L.S) + ws - 1) / ws;
     if (!L.chunk) {
-        const uint64_t target_waves = !plain ? 16384 : (esz == 8 ? 2048 : 4096);
+        const uint64_t target_waves = L.dist == kNormal ? 8192 : (L.dist == kExponential ? 4096 : (esz == 8 ? 2048 : 4096));
         uint64_t w = (target_waves + n_sblk - 1) / n_sblk;
         uint64_t w_cap = (units_max + 95) / 96;
         if (w > w_cap) w = w_cap;
