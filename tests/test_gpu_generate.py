@@ -314,3 +314,13 @@ def test_throughput_config_full_size_sampled():
     want_cols = O.generate(GEN, sub, per * 4096, threads=8).reshape(per, 4096)
     assert np.array_equal(cols, want_cols)
     del out
+
+
+@pytest.mark.parametrize("dist,dtype", [(P.MRG_NORMAL, P.MRG_F64), (P.MRG_EXPONENTIAL, P.MRG_F64),
+                                        (P.MRG_NORMAL, P.MRG_F32), (P.MRG_EXPONENTIAL, P.MRG_F32)])
+def test_transforms_large_sample(dist, dtype):
+    """2^22 transformed draws (8,192 streams x 512) in the default launch
+    shape against the oracle's long-double transforms: the library's own log
+    and sin/cos(pi t) stay inside the tolerance over a large sample."""
+    rec = O.create_streams(GEN, workloads.random_seed(61), 8192)
+    run_case(rec, 8192 * 512, dist, dtype, param=1.0 if dist == P.MRG_NORMAL else 0.75)
