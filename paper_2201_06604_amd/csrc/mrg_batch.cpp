@@ -116,6 +116,7 @@ mrg_status build(mrg_batch_plan& P) {
         const bool plain = q.dist == MRG_UNIFORM || q.dist == MRG_RAW;
         int spl = (plain && P.wide != 1) ? 16 / esz : 1;
         while (spl > 1 && (q.n_streams % spl || reinterpret_cast<uintptr_t>(q.out) % (spl * esz))) spl /= 2;
+        while (spl > 1 && 64ull * spl > q.n_streams) spl /= 2;  // a wave's streams must exist
         if (esz == 4 && spl == 2) spl = 1;  // tiles of 4-byte outputs use 1 or 4 streams per lane
         L.spl = spl;
         R.kind = static_cast<uint32_t>(batch_kind(L.dist, L.dtype, spl));

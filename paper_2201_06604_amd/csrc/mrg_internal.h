@@ -82,6 +82,7 @@ struct BatchLaunch {    // kernel arguments
     uint32_t n_req, n_tiles, n_fin;
     uint32_t tile_lo[kClasses + 1];   // class c owns tiles [tile_lo[c], tile_lo[c+1])
     uint32_t block_lo[kClasses + 1];  // and blocks [block_lo[c], block_lo[c+1])
+    uint32_t wpb;                     // waves per block of the persistent kernel
     uint64_t fin_total;
 };
 

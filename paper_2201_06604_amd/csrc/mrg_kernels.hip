@@ -374,7 +374,14 @@ __global__ void __launch_bounds__(256) finalize_kernel(uint32_t* streams, uint32
 __global__ void __launch_bounds__(256) batch_init_kernel(BatchLaunch B) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
-        for (int c = 0; c < 4; ++c) B.head->queue[c] = 0;
+        // tiles [0, waves of the class) are taken without the queue (each
+        // wave's first tile in its own class); the queue hands out the rest
+        for (int c = 0; c < kClasses; ++c) {
+            const uint32_t waves = (B.block_lo[c + 1] - B.block_lo[c]) * B.wpb;
+            const uint32_t count = B.tile_lo[c + 1] - B.tile_lo[c];
+            B.head->queue[c] = waves < count ? waves : count;
+        }
+        B.head->queue[kClasses] = 0;
         B.head->t_start = 0;
     }
     if (i < B.n_req) {
@@ -415,14 +422,17 @@ __device__ __forceinline__ void batch_tile(const GenLaunch& L, uint32_t sblk, ui
 // 0's result with readfirstlane.  Each loop's control flow is therefore
 // wave-uniform, and no lane can be left iterating on its own.
 template <int CLS>
-__device__ __forceinline__ void batch_worker(const BatchLaunch& B) {
+__device__ __forceinline__ void batch_worker(const BatchLaunch& B, uint32_t first) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t one = lane == 0 ? 1u : 0u;
     const uint32_t lo = B.tile_lo[CLS];
     const uint32_t count = B.tile_lo[CLS + 1] - lo;
     uint32_t* queue = &B.head->queue[CLS];
     for (;;) {
-        const uint32_t q = __builtin_amdgcn_readfirstlane(atomicAdd(queue, one));
+        // the first tile of a wave in its own class is its rank there (no
+        // atomic); every other tile comes from the queue
+        const uint32_t q = first != 0xffffffffu ? first : __builtin_amdgcn_readfirstlane(atomicAdd(queue, one));
+        first = 0xffffffffu;
         if (q >= count) break;
         const uint32_t t = lo + q;
         const uint32_t req = __builtin_amdgcn_readfirstlane(B.tiles[t].req);
@@ -446,7 +456,14 @@ __device__ __forceinline__ void batch_worker(const BatchLaunch& B) {
                 default: batch_tile<kBRawU32x4>(L, sblk, chunk); break;
             }
         }
-        __threadfence();  // this wave's stores are visible before the count
+        // The count must follow this wave's stores.  When a host thread
+        // watches completions (serving), it may hand a finished output to
+        // other work while this kernel still runs: the stores are released
+        // device-wide (an L2 write-back on this chip).  Otherwise consumers
+        // are ordered after the launch, whose end makes everything visible,
+        // and waiting for the stores to complete is enough.
+        if (B.host_slots) __threadfence();
+        else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         const uint32_t left = __builtin_amdgcn_readfirstlane(atomicSub(&B.slots[req].remaining, one));
         if (left == 1) {  // wave-uniform: this wave finished the request
             const uint64_t t_done = __builtin_amdgcn_s_memrealtime();
@@ -462,23 +479,34 @@ __device__ __forceinline__ void batch_worker(const BatchLaunch& B) {
     }
 }
 
+// A wave's rank among the waves of its own class, blocks ordered so that each
+// XCD (physical block b runs on XCD b mod 8) takes a contiguous run of the
+// class's tiles when the class's blocks allow it.
+__device__ __forceinline__ uint32_t home_rank(const BatchLaunch& B, int cls) {
+    const uint32_t b0 = B.block_lo[cls], nb = B.block_lo[cls + 1] - b0;
+    uint32_t i = blockIdx.x - b0;
+    if (b0 % 8 == 0 && nb % 8 == 0) i = (i % 8) * (nb / 8) + i / 8;
+    return i * B.wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
 // A block starts on its own class (blocks are shared out by estimated work),
 // then helps the other classes until every queue is empty.  The three loops
 // run one after another, so their register live ranges never overlap.
 __global__ void __launch_bounds__(256) batch_kernel(BatchLaunch B) {
+    constexpr uint32_t kNone = 0xffffffffu;
     if (blockIdx.x == 0 && threadIdx.x < 64) B.head->t_start = __builtin_amdgcn_s_memrealtime();
     if (blockIdx.x < B.block_lo[1]) {
-        batch_worker<kClsNormal>(B);
-        batch_worker<kClsExp>(B);
-        batch_worker<kClsPlain>(B);
+        batch_worker<kClsNormal>(B, home_rank(B, kClsNormal));
+        batch_worker<kClsExp>(B, kNone);
+        batch_worker<kClsPlain>(B, kNone);
     } else if (blockIdx.x < B.block_lo[2]) {
-        batch_worker<kClsExp>(B);
-        batch_worker<kClsNormal>(B);
-        batch_worker<kClsPlain>(B);
+        batch_worker<kClsExp>(B, home_rank(B, kClsExp));
+        batch_worker<kClsNormal>(B, kNone);
+        batch_worker<kClsPlain>(B, kNone);
     } else {
-        batch_worker<kClsPlain>(B);
-        batch_worker<kClsNormal>(B);
-        batch_worker<kClsExp>(B);
+        batch_worker<kClsPlain>(B, home_rank(B, kClsPlain));
+        batch_worker<kClsNormal>(B, kNone);
+        batch_worker<kClsExp>(B, kNone);
     }
 }
 
@@ -798,7 +826,9 @@ int device_cu_count() {
     return cus;
 }
 
-hipError_t launch_batch(const BatchLaunch& B, unsigned grid, unsigned block, hipStream_t s) {
+hipError_t launch_batch(const BatchLaunch& B_in, unsigned grid, unsigned block, hipStream_t s) {
+    BatchLaunch B = B_in;
+    B.wpb = block / 64;
     hipLaunchKernelGGL(batch_init_kernel, dim3(grid1d(B.n_req ? B.n_req : 1, 256)), dim3(256), 0, s, B);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
