@@ -158,7 +158,7 @@ mrg_status mrg_streams_advance(mrg_generator gen, mrg_stream* dev, size_t n, uin
  * ignored otherwise.  dev_out must be aligned to its element size.
  * n = 0 is a no-op.  Errors: MRG_E_INVALID_ARG (null pointers, n_streams = 0
  * with n > 0, dist/dtype mismatch, bad rate, misalignment, n_streams above
- * 2^31). */
+ * 2^31, 2^46 or more draws per stream). */
 mrg_status mrg_generate(mrg_generator gen, mrg_stream* dev, size_t n_streams, uint64_t n,
                         mrg_dist dist, mrg_dtype dtype, double param, void* dev_out,
                         hipStream_t stream);

@@ -200,6 +200,8 @@ mrg_status mrg_generate_ex(mrg_generator gen, mrg_stream* dev, size_t n_streams,
     if (n == 0) return ok();
     if (n_streams == 0) return fail(MRG_E_INVALID_ARG, "n_streams is 0 with n > 0");
     if (n_streams > (static_cast<size_t>(1) << 31)) return fail(MRG_E_INVALID_ARG, "n_streams above 2^31");
+    if (n / n_streams >= (static_cast<uint64_t>(1) << 46))
+        return fail(MRG_E_INVALID_ARG, "more than 2^46 draws per stream in one call");
     if (!dev || !dev_out) return fail(MRG_E_INVALID_ARG, "NULL stream or output pointer");
     const size_t esz = dtype == MRG_F64 ? 8 : 4;
     if (reinterpret_cast<uintptr_t>(dev_out) % esz)

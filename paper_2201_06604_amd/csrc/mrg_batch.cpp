@@ -75,6 +75,8 @@ mrg_status validate_request(const mrg_request& q, size_t i) {
     if (q.n == 0) return MRG_OK;
     if (q.n_streams == 0) return mrg355_fail(MRG_E_INVALID_ARG, "request %zu: no streams", i);
     if (q.n_streams > (1u << 31)) return mrg355_fail(MRG_E_INVALID_ARG, "request %zu: too many streams", i);
+    if (q.n / q.n_streams >= (static_cast<uint64_t>(1) << 46))
+        return mrg355_fail(MRG_E_INVALID_ARG, "request %zu: more than 2^46 draws per stream", i);
     if (!q.streams || !q.out) return mrg355_fail(MRG_E_INVALID_ARG, "request %zu: NULL pointer", i);
     if (reinterpret_cast<uintptr_t>(q.out) % esz_of(dtype))
         return mrg355_fail(MRG_E_INVALID_ARG, "request %zu: output misaligned", i);

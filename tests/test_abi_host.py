@@ -371,3 +371,8 @@ def test_device_creation_size_limit():
     st = P.lib().mrg_streams_create_device(1, ctypes.byref(c), (1 << 36) + 1, ctypes.c_void_p(4096), None)
     assert st == -1
     np.testing.assert_array_equal(P.creator_words(c), before)
+
+
+def test_generate_rejects_more_than_2_46_draws_per_stream():
+    assert P.mrg_generate_status(256, 1, 1 << 46, P.MRG_UNIFORM, P.MRG_F64, 1.0, 256) == -1
+    assert P.mrg_generate_status(256, 4, (1 << 48), P.MRG_UNIFORM, P.MRG_F64, 1.0, 256) == -1
