@@ -394,8 +394,8 @@ def main():
                    "out_dtype": "f64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": None if traffic is None else round(traffic / 1e9, 4),
-                     "traffic_unit": "GB per launch",
+                     "traffic": None if traffic is None else int(round(traffic)),
+                     "traffic_unit": "bytes per launch",
                      "kernel": "gen_kernel<uniform,f64>", "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": round(gen_avg_ms, 4), "source_sha256": kernel_sha()},
     }
