@@ -553,52 +553,69 @@ __device__ __forceinline__ void write_record(uint32_t* rec, const uint32_t x[6])
     }
 }
 
-// Copy jump matrices [first, first + count) of both components into LDS
-// (one burst of independent loads per block instead of a scalar load per
-// step of a lane's serial chain).
+// Copy jump matrices [first, first + count) of both components into LDS as
+// doubles (one burst of independent loads per block instead of a scalar load
+// per step of a lane's serial chain); creation then multiplies in fp64
+// (matvec_f64: the same integers as the 64-bit integer products, with a
+// third of the instructions).
 template <int G>
-__device__ __forceinline__ void stage_stream_tables(Mat3 (*dst)[2], int first, int count) {
+__device__ __forceinline__ void stage_stream_tables(double (*dst)[2][9], int first, int count) {
     const uint32_t* src0 = dev_tab<G>().stream_pow2[0][first].a;
     const uint32_t* src1 = dev_tab<G>().stream_pow2[1][first].a;
     for (int k = threadIdx.x; k < count * 9; k += blockDim.x) {
-        dst[k / 9][0].a[k % 9] = src0[k];
-        dst[k / 9][1].a[k % 9] = src1[k];
+        dst[k / 9][0][k % 9] = static_cast<double>(src0[k]);
+        dst[k / 9][1][k % 9] = static_cast<double>(src1[k]);
     }
     __syncthreads();
+}
+
+template <int G>
+__device__ __forceinline__ void apply_f64(const double (&M)[2][9], double x[6]) {
+    constexpr double m1 = G == kGen32k3a ? static_cast<double>(kM1) : static_cast<double>(kP1);
+    constexpr double m2 = G == kGen32k3a ? static_cast<double>(kM2) : static_cast<double>(kP2);
+    matvec_f64(M[0], x, m1, 1.0 / m1);
+    matvec_f64(M[1], x + 3, m2, 1.0 / m2);
 }
 
 template <int G>
 __global__ void __launch_bounds__(256) create_starts_kernel(uint32_t* out, uint64_t n_groups, uint32_t c0,
                                                             uint32_t c1, uint32_t c2, uint32_t c3, uint32_t c4,
                                                             uint32_t c5, int nbits) {
-    __shared__ Mat3 tab[58][2];  // J^(2^(b+6)), b < nbits <= 58
+    __shared__ double tab[58][2][9];  // J^(2^(b+6)), b < nbits <= 58
     stage_stream_tables<G>(tab, 6, nbits);
     const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= n_groups) return;
-    uint32_t x[6] = {c0, c1, c2, c3, c4, c5};
+    double x[6] = {static_cast<double>(c0), static_cast<double>(c1), static_cast<double>(c2),
+                   static_cast<double>(c3), static_cast<double>(c4), static_cast<double>(c5)};
     for (int b = 0; b < nbits; ++b)  // stream index 64 g: bit b of g is bit b + 6
-        if ((g >> b) & 1) dev_apply<G>(tab[b][0], tab[b][1], x);
-    write_record<G>(out + g * 64 * 18, x);
+        if ((g >> b) & 1) apply_f64<G>(tab[b], x);
+    uint32_t w[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) w[k] = static_cast<uint32_t>(x[k]);
+    write_record<G>(out + g * 64 * 18, w);
 }
 
 // The block's 256 records (18 KiB, contiguous in memory) are assembled in LDS
 // and written with coalesced dword stores.
 template <int G>
 __global__ void __launch_bounds__(256) create_lanes_kernel(uint32_t* out, uint64_t n) {
-    __shared__ Mat3 tab[6][2];  // J^(2^b), b < 6
+    __shared__ double tab[6][2][9];  // J^(2^b), b < 6
     __shared__ uint32_t recs[256 * 18];
     stage_stream_tables<G>(tab, 0, 6);
     const uint64_t first_i = static_cast<uint64_t>(blockIdx.x) * 256;
     const uint64_t i = first_i + threadIdx.x;
     if (i < n) {
         const uint32_t* start = out + (i & ~static_cast<uint64_t>(63)) * 18;  // written by create_starts_kernel
-        uint32_t x[6];
+        double x[6];
 #pragma unroll
-        for (int w = 0; w < 6; ++w) x[w] = start[w];
+        for (int w = 0; w < 6; ++w) x[w] = static_cast<double>(start[w]);
 #pragma unroll
         for (int b = 0; b < 6; ++b)
-            if ((i >> b) & 1) dev_apply<G>(tab[b][0], tab[b][1], x);
-        write_record<G>(recs + threadIdx.x * 18, x);
+            if ((i >> b) & 1) apply_f64<G>(tab[b], x);
+        uint32_t w[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) w[k] = static_cast<uint32_t>(x[k]);
+        write_record<G>(recs + threadIdx.x * 18, w);
     }
     __syncthreads();  // every group start of this block has been read
     const uint64_t n_here = n - first_i < 256 ? n - first_i : 256;

@@ -165,6 +165,34 @@ MRG_HD constexpr void matvec(const Mat3& M, uint32_t v[3], uint32_t c) {
     v[2] = t[2];
 }
 
+// v <- M v (mod m) in fp64, exactly, for m < 2^32, entries of M and v below
+// m.  Each word of v is split into 16-bit halves, so every product is below
+// 2^48 and each row's two 3-term sums below 2^50; a sum A is reduced as
+// A - rint(A/m) m (one FMA, exact: the nearest quotient is off by at most
+// one and the result stays below m in magnitude), the halves recombine as
+// a*2^16 + B < 2^51, and a final floor step maps into [0, m).
+// The same integers as matvec<B>(), with floating-point multiply-adds.
+MRG_HD inline double f64_mod_near(double a, double m, double inv_m) {
+    return __builtin_fma(-__builtin_rint(a * inv_m), m, a);
+}
+
+MRG_HD inline void matvec_f64(const double M[9], double v[3], double m, double inv_m) {
+    double hi[3], lo[3], t[3];
+    for (int k = 0; k < 3; ++k) {
+        hi[k] = __builtin_floor(v[k] * (1.0 / 65536.0));
+        lo[k] = __builtin_fma(-hi[k], 65536.0, v[k]);
+    }
+    for (int r = 0; r < 3; ++r) {
+        const double a = __builtin_fma(M[r * 3 + 2], hi[2], __builtin_fma(M[r * 3 + 1], hi[1], M[r * 3] * hi[0]));
+        const double b = __builtin_fma(M[r * 3 + 2], lo[2], __builtin_fma(M[r * 3 + 1], lo[1], M[r * 3] * lo[0]));
+        const double c = f64_mod_near(__builtin_fma(f64_mod_near(a, m, inv_m), 65536.0, b), m, inv_m);
+        t[r] = __builtin_fma(-__builtin_floor(c * inv_m), m, c);  // [0, m)
+    }
+    v[0] = t[0];
+    v[1] = t[1];
+    v[2] = t[2];
+}
+
 // Per-bit jump tables: step_pow2[j][b] = A_j^(2^b), stream_pow2[j][b] =
 // A_j^(2^(Z+b)) (b < 64; Z = 127 or 134), substream[j] = A_j^(2^76 or 2^72).
 struct JumpTables {
