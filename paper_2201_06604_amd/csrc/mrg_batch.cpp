@@ -50,9 +50,16 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 size_t esz_of(mrg_dtype dt) { return dt == MRG_F64 ? 8 : 4; }
 
-// Estimated time of one draw unit of one stream, relative units: the whole
-// MI355X runs about 700 G f64 uniforms/s (store-bound), 1.4 T f32 uniforms/s,
-// 325 G normals/s and 300 G exponentials/s (fp64 transcendentals).
+// Estimated time of one draw unit of one stream, relative units, from the
+// rates of plain launches over many streams: about 700 G f64 uniforms/s
+// (store-bound), 1.4 T f32 uniforms/s, 325 G normals/s and 300 G
+// exponentials/s (the transcendental rates before the library's own log and
+// sin/cos).  They set the order of the tiles and each class's share of the
+// blocks.  Weighting the VALU-bound classes this heavily is deliberate: an
+// A/B on the 4,096-request mix against the rates each class reaches inside
+// the batch (uniforms ~330-440 G/s, normals ~280-330, exponentials
+// ~335-450) gave 10.53-10.55 ms against 10.77-10.80 ms, since store-bound
+// uniform tiles run well beside the transform-heavy ones.
 double unit_cost(int dist, int dtype) {
     switch (dist) {
         case kNormal: return 2.0 / 325.0;  // per pair
