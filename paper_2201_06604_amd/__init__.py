@@ -180,6 +180,22 @@ def _dptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _need(t, n_bytes, what, esz=None):
+    """A device tensor `t` must hold n_bytes contiguous bytes (and, when esz
+    is given, elements of that size): the library cannot see buffer sizes,
+    so a short buffer would be written past its end."""
+    if t is None or isinstance(t, int):
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{what}: expected a device (CUDA) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: expected a contiguous tensor")
+    if esz is not None and t.element_size() != esz:
+        raise ValueError(f"{what}: expected {esz}-byte elements, got {t.element_size()}")
+    if t.numel() * t.element_size() < n_bytes:
+        raise ValueError(f"{what}: needs {n_bytes} bytes, has {t.numel() * t.element_size()}")
+
+
 def _seed_arr(seed):
     a = np.ascontiguousarray(np.asarray(seed, dtype=np.uint64).astype(np.uint32))
     if a.shape != (6,) or not np.array_equal(a.astype(np.uint64), np.asarray(seed, dtype=np.uint64)):
@@ -227,17 +243,20 @@ def mrg_streams_create_device(creator, n, out=None, gen=MRG_GEN_MRG32K3A, stream
     the device; allocated when None); `creator` advances."""
     if out is None:
         out = new_streams_tensor(max(n, 1))
+    _need(out, n * REC_WORDS * 4, "stream records")
     _check(lib().mrg_streams_create_device(gen, ctypes.byref(creator), n, _dptr(out), _stream(stream)))
     return out
 
 
 def mrg_streams_reset(streams, kind, n=None, gen=MRG_GEN_MRG32K3A, stream=None):
     n = streams.shape[0] if n is None else n
+    _need(streams, n * REC_WORDS * 4, "stream records")
     _check(lib().mrg_streams_reset(gen, _dptr(streams), n, kind, _stream(stream)))
 
 
 def mrg_streams_advance(streams, steps, n=None, gen=MRG_GEN_MRG32K3A, stream=None):
     n = streams.shape[0] if n is None else n
+    _need(streams, n * REC_WORDS * 4, "stream records")
     _check(lib().mrg_streams_advance(gen, _dptr(streams), n, steps, _stream(stream)))
 
 
@@ -258,6 +277,8 @@ def mrg_generate(streams, n, dist=MRG_UNIFORM, dtype=MRG_F64, param=1.0, out=Non
     S = streams.shape[0] if n_streams is None else n_streams
     if out is None:
         out = new_output(n, dtype)
+    _need(streams, S * REC_WORDS * 4, "stream records")
+    _need(out, n * (8 if dtype == MRG_F64 else 4), "output", 8 if dtype == MRG_F64 else 4)
     if cfg is None:
         st = lib().mrg_generate(gen, _dptr(streams), S, n, dist, dtype, param, _dptr(out),
                                 _stream(stream))
@@ -279,6 +300,7 @@ def mrg_generate_status(streams_ptr, n_streams, n, dist, dtype, param, out_ptr,
 def mrg_streams_export(streams, n=None, creator=None, gen=MRG_GEN_MRG32K3A, stream=None):
     """Save n device records (+ creator) into a bytes object."""
     n = streams.shape[0] if n is None else n
+    _need(streams, n * REC_WORDS * 4, "stream records")
     need = ctypes.c_size_t()
     _check(lib().mrg_streams_export_size(n, 1 if creator is not None else 0, ctypes.byref(need)))
     buf = ctypes.create_string_buffer(need.value)
@@ -311,8 +333,8 @@ def mrg_generate_paper(streams, nrow, ncol, G0, G1, dist=MRG_UNIFORM, dtype=MRG_
     if out is None:
         out = torch.empty((max(nrow, 1), max(npad, 1)), dtype=getattr(torch, _TORCH_DT[dtype]),
                           device=streams.device)
-    if out.numel() < nrow * npad or not out.is_contiguous():
-        raise ValueError("out must be a contiguous buffer of nrow * npad elements")
+    esz = 8 if dtype == MRG_F64 else 4
+    _need(out, nrow * npad * esz, "output", esz)
     _check(lib().mrg_generate_paper(gen, _dptr(streams), streams.shape[0], nrow, ncol, npad, G0, G1, dist, dtype,
                                     param, _dptr(out), _stream(stream)))
     return out
@@ -382,6 +404,8 @@ def as_u32(t):
 def make_request(streams, n, dist, dtype, param=1.0, out=None, n_streams=None):
     """mrg_request for device tensors `streams` ((S,18) int32) and `out`."""
     S = streams.shape[0] if n_streams is None else n_streams
+    _need(streams, S * REC_WORDS * 4, "stream records")
+    _need(out, n * (8 if dtype == MRG_F64 else 4), "output", 8 if dtype == MRG_F64 else 4)
     return mrg_request(streams.data_ptr() if streams is not None else None, S, n, dist, dtype, param,
                        out.data_ptr() if out is not None else None)
 

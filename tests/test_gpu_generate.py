@@ -324,3 +324,21 @@ def test_transforms_large_sample(dist, dtype):
     and sin/cos(pi t) stay inside the tolerance over a large sample."""
     rec = O.create_streams(GEN, workloads.random_seed(61), 8192)
     run_case(rec, 8192 * 512, dist, dtype, param=1.0 if dist == P.MRG_NORMAL else 0.75)
+
+
+def test_short_buffers_are_rejected_before_launch():
+    """The binding refuses buffers that cannot hold the result (the C ABI
+    cannot see device buffer sizes): nothing is launched, nothing moves."""
+    rec = O.create_streams(GEN, workloads.random_seed(62), 100)
+    d = dev_streams(rec)
+    short = torch.empty(99, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        P.mrg_generate(d, 100, out=short)
+    with pytest.raises(ValueError):  # wrong element size for f64
+        P.mrg_generate(d, 10, out=torch.empty(10, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):  # 100 records claimed, 50 given
+        P.mrg_generate(d[:50], 100, n_streams=100)
+    with pytest.raises(ValueError):
+        P.mrg_streams_advance(d[:10], 5, n=11)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(P.as_u32(d), rec)
