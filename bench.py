@@ -128,9 +128,60 @@ def cpu_baseline(seed):
     t0 = time.perf_counter()
     O.generate(O.MRG32K3A, rec, n, O.UNIFORM, O.F64, 1.0, threads=threads)
     dt = time.perf_counter() - t0
+    # one thread, on the first 16,384 streams (1/16 of the workload)
+    sub = O.create_streams(O.MRG32K3A, seed.copy(), 16384)
+    t1 = time.perf_counter()
+    O.generate(O.MRG32K3A, sub, 16384 * PER_STREAM, O.UNIFORM, O.F64, 1.0, threads=1)
+    dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n / dt / 1e9, "unit": "GSamples/s", "cores": threads, "kind": "oracle",
             "sample": f"{S_sample} streams x {PER_STREAM} fp64 uniforms, the whole workload "
-                      f"({n} draws, {dt:.2f} s wall on {threads} threads)"}
+                      f"({n} draws, {dt:.2f} s wall on {threads} threads)",
+            "single_thread": {"value": 16384 * PER_STREAM / dt1 / 1e9, "unit": "GSamples/s",
+                              "sample": f"16384 streams x {PER_STREAM} fp64 uniforms ({dt1:.2f} s)"},
+            "cpu_model": model, "nproc": os.cpu_count()}
+
+
+def bench_small(torch, P, workloads, reps=50):
+    """The paper-shaped small case: seed 12345 x 6, 1,024 streams created on
+    the device, 1,024 fp64 uniforms each (2^20): launch-bound, so latency per
+    call (median and min of 50, HIP events), and the oracle on one core."""
+    import oracle as O
+    st = P.new_streams_tensor(1024)
+    out = torch.empty(1 << 20, dtype=torch.float64, device="cuda")
+
+    def create_gen():
+        c = P.mrg_creator_init(workloads.PAPER_SEED)
+        P.mrg_streams_create_device(c, 1024, out=st)
+        P.mrg_generate(st, 1 << 20, P.MRG_UNIFORM, P.MRG_F64, out=out)
+
+    both, gen = [], []
+    for _ in range(5):
+        create_gen()
+    for _ in range(reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        c = P.mrg_creator_init(workloads.PAPER_SEED)
+        P.mrg_streams_create_device(c, 1024, out=st)
+        e[1].record()
+        P.mrg_generate(st, 1 << 20, P.MRG_UNIFORM, P.MRG_F64, out=out)
+        e[2].record()
+        torch.cuda.synchronize()
+        both.append(e[0].elapsed_time(e[2]) * 1e3)
+        gen.append(e[1].elapsed_time(e[2]) * 1e3)
+    rec = O.create_streams(O.MRG32K3A, np.array(workloads.PAPER_SEED, dtype=np.uint32), 1024)
+    t0 = time.perf_counter()
+    O.generate(O.MRG32K3A, rec, 1 << 20, O.UNIFORM, O.F64, 1.0, threads=1)
+    oracle_ms = (time.perf_counter() - t0) * 1e3
+    return {"workload": "seed 12345 x 6, 1,024 streams created on the device, 1,024 fp64 uniforms each",
+            "create_and_generate_us": {"median": round(float(np.median(both)), 1), "min": round(float(min(both)), 1)},
+            "generate_us": {"median": round(float(np.median(gen)), 1), "min": round(float(min(gen)), 1)},
+            "oracle_one_core_ms": round(oracle_ms, 1)}
 
 
 def bench_batched(torch, P, workloads, reps=3):
@@ -298,7 +349,7 @@ def bench_paper(torch, P, workloads, out, reps=5):
     return res
 
 
-def bench_serving(torch, P, workloads, rates=(2000, 10000, 50000), duration=1.0):
+def bench_serving(torch, P, workloads, rates=(2000, 5000, 10000, 20000, 50000), duration=1.0):
     """The request loop: Poisson arrivals from 256 sessions (64 device
     streams each), lengths log-uniform in [1e2, 1e6] fp64 normals, a 32 GB
     output pool; continuous batching on 4 HIP streams against one plain
@@ -311,11 +362,14 @@ def bench_serving(torch, P, workloads, rates=(2000, 10000, 50000), duration=1.0)
         for mode, name in ((0, "batched"), (1, "plain")):
             srv = P.Server(256, workloads.random_seed(), pool, mode=mode)
             lat, span = srv.drive((t * 1e9).astype(np.uint64), sess, lens)
+            peak = srv.stats()["pool_peak"]
             srv.close()
             lat_ms = lat / 1e6
             row[name] = {"GSamples_per_s": round(float(lens.sum()) / (span / 1e9) / 1e9, 3),
                          "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
-                         "p99_ms": round(float(np.percentile(lat_ms, 99)), 3)}
+                         "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+                         "p999_ms": round(float(np.percentile(lat_ms, 99.9)), 3),
+                         "pool_peak_MB": round(peak / 1e6, 1)}
         out[f"{rate}_per_s"] = dict(requests=int(len(t)), **row)
     del pool
     return {"workload": f"Poisson arrivals for {duration:g} s, 256 sessions x 64 streams, lengths log-uniform "
@@ -397,7 +451,9 @@ def main():
                      "traffic": None if traffic is None else int(round(traffic)),
                      "traffic_unit": "bytes per launch",
                      "kernel": "gen_kernel<uniform,f64>", "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_ms": round(gen_avg_ms, 4), "source_sha256": kernel_sha()},
+                     "avg_launch_ms": round(gen_avg_ms, 4),
+                     "launch_ms_median": round(float(np.median(gen_ms)), 4),
+                     "launch_ms_min": round(float(min(gen_ms)), 4), "source_sha256": kernel_sha()},
     }
 
     # store-only ceiling: torch's fill of the same 8 GiB buffer
@@ -410,6 +466,7 @@ def main():
     torch.cuda.synchronize()
     fill_ms = fe[0].elapsed_time(fe[1]) / 5
     res["store_only_fill_GBps"] = round(N * 8 / (fill_ms * 1e-3) / 1e9, 1)
+    res["achieved_vs_store_only"] = round(achieved / res["store_only_fill_GBps"], 3)
 
     if not args.no_variants:
         var = {}
@@ -429,6 +486,8 @@ def main():
                          "GB_per_s": round(N * esz / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4)}
         del out32
         res["variants"] = var
+
+    res["small"] = bench_small(torch, P, workloads)
 
     if not args.no_batch:
         res["batched"] = bench_batched(torch, P, workloads)
