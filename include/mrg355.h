@@ -104,7 +104,10 @@ typedef enum {
  *                    the largest not above it that keeps a store within 16
  *                    bytes and divides n_streams, with the output aligned to
  *                    the store width
- *   xcd_remap        1 = give each XCD a contiguous range of row segments   */
+ *   xcd_remap        1 = give each XCD a contiguous range of row segments
+ *   lockstep         1 = the waves of a block write each draw index together
+ *                    (a workgroup barrier per row); ignored unless every wave
+ *                    of the grid holds 64*streams_per_lane streams           */
 typedef struct {
     uint32_t block;
     uint32_t chunk;
@@ -112,6 +115,7 @@ typedef struct {
     uint32_t arith;
     uint32_t streams_per_lane;
     uint32_t xcd_remap;
+    uint32_t lockstep;
 } mrg_launch_cfg;
 
 int         mrg_abi_version(void);
@@ -168,6 +172,14 @@ mrg_status mrg_generate(mrg_generator gen, mrg_stream* dev, size_t n_streams, ui
 mrg_status mrg_generate_ex(mrg_generator gen, mrg_stream* dev, size_t n_streams, uint64_t n,
                            mrg_dist dist, mrg_dtype dtype, double param, void* dev_out,
                            const mrg_launch_cfg* cfg, hipStream_t stream);
+
+/* Host only: the launch shape mrg_generate_ex would use for these arguments
+ * and `cfg` (NULL = automatic) with an output aligned to 256 bytes, written
+ * to host struct `*resolved` (all zero for n = 0; arith 0 for MRG31k3p,
+ * which has one arithmetic form).  Same argument checks and errors as
+ * mrg_generate_ex, pointers aside; nothing is launched. */
+mrg_status mrg_generate_plan(mrg_generator gen, size_t n_streams, uint64_t n, mrg_dist dist, mrg_dtype dtype,
+                             double param, const mrg_launch_cfg* cfg, mrg_launch_cfg* resolved);
 
 /* Save/restore (Section 2.2, saveRDS/readRDS example).  Byte format,
  * little-endian: "MRG3", u32 version = 1, u32 generator, u32 flags (bit 0:

@@ -39,10 +39,11 @@ class mrg_creator(ctypes.Structure):
 class mrg_launch_cfg(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
                 ("nontemporal", ctypes.c_uint32), ("arith", ctypes.c_uint32),
-                ("streams_per_lane", ctypes.c_uint32), ("xcd_remap", ctypes.c_uint32)]
+                ("streams_per_lane", ctypes.c_uint32), ("xcd_remap", ctypes.c_uint32),
+                ("lockstep", ctypes.c_uint32)]
 
 
-CFG_KEYS = ("block", "chunk", "nontemporal", "arith", "streams_per_lane", "xcd_remap")
+CFG_KEYS = ("block", "chunk", "nontemporal", "arith", "streams_per_lane", "xcd_remap", "lockstep")
 
 
 def launch_cfg(cfg):
@@ -105,6 +106,8 @@ def lib():
             "mrg_generate": (i32, [i32, vp, sz, u64, i32, i32, ctypes.c_double, vp, vp]),
             "mrg_generate_ex": (i32, [i32, vp, sz, u64, i32, i32, ctypes.c_double, vp,
                                       ctypes.POINTER(mrg_launch_cfg), vp]),
+            "mrg_generate_plan": (i32, [i32, sz, u64, i32, i32, ctypes.c_double,
+                                        ctypes.POINTER(mrg_launch_cfg), ctypes.POINTER(mrg_launch_cfg)]),
             "mrg_streams_export_size": (i32, [sz, i32, ctypes.POINTER(sz)]),
             "mrg_streams_export": (i32, [i32, vp, sz, crp, vp, sz, ctypes.POINTER(sz), vp]),
             "mrg_streams_import": (i32, [i32, vp, sz, vp, sz, ctypes.POINTER(sz), crp, vp]),
@@ -146,7 +149,7 @@ def lib():
 
 EXPORTED = ["mrg_abi_version", "mrg_status_string", "mrg_last_error", "mrg_seed_check",
             "mrg_creator_init", "mrg_streams_create_host", "mrg_streams_create_device",
-            "mrg_streams_reset", "mrg_streams_advance", "mrg_generate", "mrg_generate_ex",
+            "mrg_streams_reset", "mrg_streams_advance", "mrg_generate", "mrg_generate_ex", "mrg_generate_plan",
             "mrg_streams_export_size", "mrg_streams_export", "mrg_streams_import",
             "mrg_generate_paper", "mrg_tables_sample", "mrg_fisher_sim", "mrg_fisher_pvalue",
             "mrg_batch_plan_create", "mrg_batch_plan_destroy", "mrg_batch_workspace_size",
@@ -288,6 +291,16 @@ def mrg_generate(streams, n, dist=MRG_UNIFORM, dtype=MRG_F64, param=1.0, out=Non
                                    ctypes.byref(c), _stream(stream))
     _check(st)
     return out
+
+
+def mrg_generate_plan(n_streams, n, dist=MRG_UNIFORM, dtype=MRG_F64, param=1.0, cfg=None,
+                      gen=MRG_GEN_MRG32K3A):
+    """The launch shape mrg_generate would use (host only, nothing runs), as
+    a dict with the keys of CFG_KEYS."""
+    res = mrg_launch_cfg()
+    c = None if cfg is None else ctypes.byref(launch_cfg(cfg))
+    _check(lib().mrg_generate_plan(gen, n_streams, n, dist, dtype, param, c, ctypes.byref(res)))
+    return {k: int(getattr(res, k)) for k in CFG_KEYS}
 
 
 def mrg_generate_status(streams_ptr, n_streams, n, dist, dtype, param, out_ptr,

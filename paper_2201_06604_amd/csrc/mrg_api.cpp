@@ -167,9 +167,12 @@ mrg_status mrg_streams_advance(mrg_generator gen, mrg_stream* dev, size_t n, uin
     return ok();
 }
 
-mrg_status mrg_generate_ex(mrg_generator gen, mrg_stream* dev, size_t n_streams, uint64_t n,
-                           mrg_dist dist, mrg_dtype dtype, double param, void* dev_out,
-                           const mrg_launch_cfg* cfg, hipStream_t stream) {
+// Validates a generate call's shape and launch cfg and fills L except its
+// pointers.  *noop is set for n == 0 (nothing to launch).
+static mrg_status generate_shape(mrg_generator gen, size_t n_streams, uint64_t n, mrg_dist dist,
+                                 mrg_dtype dtype, double param, const mrg_launch_cfg* cfg, GenLaunch& L,
+                                 bool* noop) {
+    *noop = false;
     if (mrg_status st = check_gen(gen)) return st;
     if (dist != MRG_UNIFORM && dist != MRG_NORMAL && dist != MRG_EXPONENTIAL && dist != MRG_RAW)
         return fail(MRG_E_INVALID_ARG, "unknown distribution %d", static_cast<int>(dist));
@@ -179,7 +182,7 @@ mrg_status mrg_generate_ex(mrg_generator gen, mrg_stream* dev, size_t n_streams,
         return fail(MRG_E_INVALID_ARG, "MRG_RAW pairs with MRG_U32 only, and MRG_U32 with MRG_RAW only");
     if (dist == MRG_EXPONENTIAL && !(std::isfinite(param) && param > 0.0))
         return fail(MRG_E_INVALID_ARG, "exponential rate must be finite and > 0");
-    GenLaunch L{};
+    L = GenLaunch{};
     if (cfg) {
         uint32_t b = cfg->block;
         if (b != 0 && b != 64 && b != 128 && b != 256 && b != 512 && b != 1024)
@@ -190,25 +193,23 @@ mrg_status mrg_generate_ex(mrg_generator gen, mrg_stream* dev, size_t n_streams,
         if (spl != 0 && spl != 1 && spl != 2 && spl != 4)
             return fail(MRG_E_INVALID_ARG, "streams_per_lane must be 0, 1, 2 or 4");
         if (cfg->xcd_remap > 1) return fail(MRG_E_INVALID_ARG, "xcd_remap must be 0 or 1");
+        if (cfg->lockstep > 1) return fail(MRG_E_INVALID_ARG, "lockstep must be 0 or 1");
         L.block = static_cast<int>(b);
         L.chunk = cfg->chunk;
         L.nontemporal = static_cast<int>(cfg->nontemporal);
         L.arith = static_cast<int>(cfg->arith);
         L.spl = static_cast<int>(spl);
         L.xcd = static_cast<int>(cfg->xcd_remap);
+        L.lock = static_cast<int>(cfg->lockstep);
     }
-    if (n == 0) return ok();
+    if (n == 0) {
+        *noop = true;
+        return ok();
+    }
     if (n_streams == 0) return fail(MRG_E_INVALID_ARG, "n_streams is 0 with n > 0");
     if (n_streams > (static_cast<size_t>(1) << 31)) return fail(MRG_E_INVALID_ARG, "n_streams above 2^31");
     if (n / n_streams >= (static_cast<uint64_t>(1) << 46))
         return fail(MRG_E_INVALID_ARG, "more than 2^46 draws per stream in one call");
-    if (!dev || !dev_out) return fail(MRG_E_INVALID_ARG, "NULL stream or output pointer");
-    const size_t esz = dtype == MRG_F64 ? 8 : 4;
-    if (reinterpret_cast<uintptr_t>(dev_out) % esz)
-        return fail(MRG_E_INVALID_ARG, "output not aligned to its element size");
-    if (reinterpret_cast<uintptr_t>(dev) % 4) return fail(MRG_E_INVALID_ARG, "streams misaligned");
-    L.streams = reinterpret_cast<uint32_t*>(dev);
-    L.out = dev_out;
     L.S = static_cast<uint32_t>(n_streams);
     L.q = n / n_streams;
     L.r = static_cast<uint32_t>(n % n_streams);
@@ -216,9 +217,48 @@ mrg_status mrg_generate_ex(mrg_generator gen, mrg_stream* dev, size_t n_streams,
     L.dtype = static_cast<int>(dtype);
     L.param = dist == MRG_EXPONENTIAL ? 1.0 / param : 1.0;
     if (gen == MRG_GEN_MRG31K3P) L.arith = kArith31;  // its own engine; cfg->arith applies to MRG32k3a
+    return ok();
+}
+
+mrg_status mrg_generate_ex(mrg_generator gen, mrg_stream* dev, size_t n_streams, uint64_t n,
+                           mrg_dist dist, mrg_dtype dtype, double param, void* dev_out,
+                           const mrg_launch_cfg* cfg, hipStream_t stream) {
+    GenLaunch L;
+    bool noop;
+    if (mrg_status st = generate_shape(gen, n_streams, n, dist, dtype, param, cfg, L, &noop)) return st;
+    if (noop) return ok();
+    if (!dev || !dev_out) return fail(MRG_E_INVALID_ARG, "NULL stream or output pointer");
+    const size_t esz = dtype == MRG_F64 ? 8 : 4;
+    if (reinterpret_cast<uintptr_t>(dev_out) % esz)
+        return fail(MRG_E_INVALID_ARG, "output not aligned to its element size");
+    if (reinterpret_cast<uintptr_t>(dev) % 4) return fail(MRG_E_INVALID_ARG, "streams misaligned");
+    L.streams = reinterpret_cast<uint32_t*>(dev);
+    L.out = dev_out;
     plan_generate(L);
     hipError_t e = launch_generate(L, stream);
     if (e != hipSuccess) return hip_fail(e, "generate launch");
+    return ok();
+}
+
+mrg_status mrg_generate_plan(mrg_generator gen, size_t n_streams, uint64_t n, mrg_dist dist, mrg_dtype dtype,
+                             double param, const mrg_launch_cfg* cfg, mrg_launch_cfg* resolved) {
+    if (!resolved) return fail(MRG_E_INVALID_ARG, "NULL resolved cfg");
+    GenLaunch L;
+    bool noop;
+    if (mrg_status st = generate_shape(gen, n_streams, n, dist, dtype, param, cfg, L, &noop)) return st;
+    *resolved = mrg_launch_cfg{};
+    if (noop) return ok();
+    // an output address aligned to 256 bytes, as device allocations are; only
+    // its alignment is looked at
+    L.out = reinterpret_cast<void*>(static_cast<uintptr_t>(256));
+    plan_generate(L);
+    resolved->block = static_cast<uint32_t>(L.block);
+    resolved->chunk = L.chunk;
+    resolved->nontemporal = static_cast<uint32_t>(L.nontemporal);
+    resolved->arith = L.arith == kArith31 ? 0u : static_cast<uint32_t>(L.arith);
+    resolved->streams_per_lane = static_cast<uint32_t>(L.spl);
+    resolved->xcd_remap = static_cast<uint32_t>(L.xcd);
+    resolved->lockstep = static_cast<uint32_t>(L.lock);
     return ok();
 }
 

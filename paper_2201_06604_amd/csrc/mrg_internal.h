@@ -29,6 +29,7 @@ struct GenLaunch {
     int xcd;             // 1 = XCD-contiguous block order
     uint64_t offset;     // steps every stream is advanced before its first draw
     int no_writeback;    // 1 = leave the stream records untouched (served requests)
+    int lock;            // 1 = the waves of a block write each row together (barrier per row)
 };
 
 // Resolve chunk/n_chunks/block/arith left at 0 to the automatic choice.

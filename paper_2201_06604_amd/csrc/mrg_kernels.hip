@@ -157,12 +157,26 @@ __device__ __forceinline__ void store_1(__amdgpu_buffer_rsrc_t r, uint32_t voff,
 }
 
 // ------------------------------------------------------------ generate
+// Draw units [u0, kend) of chunk `by` are the main-loop rows: every stream of
+// the request has them (rows from kend on are the ragged tail).  Both bounds
+// depend on the chunk only, so every wave of a block runs the same rows.
+template <int DIST>
+__device__ __forceinline__ void main_rows(const GenLaunch& L, uint32_t by, uint64_t& u0, uint64_t& u1,
+                                          uint64_t& kend) {
+    const uint64_t cnt_max = L.q + (L.r ? 1 : 0);
+    const uint64_t units_max = DIST == kNormal ? (cnt_max + 1) / 2 : cnt_max;
+    const uint64_t full = DIST == kNormal ? L.q / 2 : L.q;  // units every stream completes
+    u0 = static_cast<uint64_t>(by) * L.chunk;
+    u1 = min(u0 + L.chunk, units_max);
+    kend = max(u0, min(u1, full));
+}
+
 // One wave = 64 lanes x SPL consecutive streams, one chunk of draw indices.
 // Lane l owns streams s0 .. s0+SPL-1, s0 = first + l*SPL, and stores their
 // SPL values of a draw index with one SPL*esz-byte store.
 // One wave's share of one request: stream block `sblk` (64*SPL streams),
 // draw units [by*chunk, (by+1)*chunk).  Wave-uniform arguments.
-template <int DIST, int DTYPE, int ARITH, int SPL, bool NT>
+template <int DIST, int DTYPE, int ARITH, int SPL, bool NT, bool LOCK = false>
 __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uint32_t by) {
     using Engine = typename std::conditional<
         ARITH == kArith31, Engine31,
@@ -185,12 +199,11 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
         cnt[i] = L.q + (s0 + i < L.r ? 1 : 0);
         units[i] = DIST == kNormal ? (cnt[i] + 1) / 2 : cnt[i];
     }
-    const uint64_t cnt_max = L.q + (L.r ? 1 : 0);
-    const uint64_t units_max = DIST == kNormal ? (cnt_max + 1) / 2 : cnt_max;
-    const uint64_t full = DIST == kNormal ? L.q / 2 : L.q;  // units every stream completes
-    const uint64_t u0 = static_cast<uint64_t>(by) * L.chunk;
-    if (u0 >= units[0]) return;  // counts do not increase with s: stream s0 has the most
-    const uint64_t u1 = min(u0 + L.chunk, units_max);
+    uint64_t u0, u1, kend;
+    main_rows<DIST>(L, by, u0, u1, kend);
+    // Counts do not increase with s: stream s0 has the most.  A lane leaving
+    // here has u0 >= q (>= q/2 for pairs), so kend == u0: no main-loop rows.
+    if (u0 >= units[0]) return;
 
     Engine e[SPL];
 #pragma unroll
@@ -210,7 +223,6 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
     const uint32_t nrec = rest > 0xffffffffull ? 0xffffffffu : static_cast<uint32_t>(rest);
     const uint32_t voff = lane * SPL * ESZ;
     const char* row = static_cast<const char*>(L.out) + (u0 * kSpu * S + first) * ESZ;
-    const uint64_t kend = max(u0, min(u1, full));
     uint64_t k = u0;
 
     if constexpr (DIST == kNormal) {
@@ -230,6 +242,7 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
             row += rowstep;
             store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, py);
             row += rowstep;
+            if constexpr (LOCK) __builtin_amdgcn_s_barrier();
         };
         for (; k + 3 <= kend; k += 3) {
             pair([](Engine& g, double& x, double& y) {
@@ -292,10 +305,13 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
             }
             store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, p0);
             row += rowstep;
+            if constexpr (LOCK) __builtin_amdgcn_s_barrier();
             store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, p1);
             row += rowstep;
+            if constexpr (LOCK) __builtin_amdgcn_s_barrier();
             store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, p2);
             row += rowstep;
+            if constexpr (LOCK) __builtin_amdgcn_s_barrier();
         }
         for (; k < kend; ++k) {
             Pack<T, SPL> p;
@@ -330,7 +346,13 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
     }
 }
 
-template <int DIST, int DTYPE, int ARITH, int SPL, bool NT>
+// LOCK: the waves of a block pass a barrier after each row of the main
+// loops (three per unrolled iteration), so a block writes 64*SPL*waves
+// consecutive elements of a row at once.  All waves of a block run the same
+// main-loop rows (main_rows); a wave past the last stream block stays to
+// pass the same barriers, and lanes past the last stream leave without
+// ending their wave (a wave's lane 0 always holds a stream).
+template <int DIST, int DTYPE, int ARITH, int SPL, bool NT, bool LOCK>
 __global__ void __launch_bounds__(1024) gen_kernel(GenLaunch L) {
     // Block -> (stream block, chunk).  With xcd remapping, consecutive logical
     // blocks (neighbouring row segments) land on one XCD, whose L2 then sees
@@ -345,8 +367,19 @@ __global__ void __launch_bounds__(1024) gen_kernel(GenLaunch L) {
     }
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t sblk = bx * (blockDim.x >> 6) + wave;
-    if (sblk >= (L.S + 64 * SPL - 1) / (64 * SPL)) return;
-    run_chunk<DIST, DTYPE, ARITH, SPL, NT>(L, sblk, by);
+    if (sblk >= (L.S + 64 * SPL - 1) / (64 * SPL)) {
+        if constexpr (LOCK) {
+            uint64_t u0, u1, kend;
+            main_rows<DIST>(L, by, u0, u1, kend);
+            for (uint64_t k = u0; k + 3 <= kend; k += 3) {
+                __builtin_amdgcn_s_barrier();
+                __builtin_amdgcn_s_barrier();
+                __builtin_amdgcn_s_barrier();
+            }
+        }
+        return;
+    }
+    run_chunk<DIST, DTYPE, ARITH, SPL, NT, LOCK>(L, sblk, by);
 }
 
 // cur <- A^(steps consumed) cur for every stream, after a chunked launch:
@@ -715,10 +748,15 @@ hipError_t launch_advance(int gen, uint32_t* streams, uint64_t n, uint64_t steps
 // Automatic launch shape, from measurements on MI355X at 2^30 draws over
 // 262,144 streams (interleaved medians):
 //   f64 uniforms   2 streams/lane (16-byte stores), ~2 waves per SIMD, each
-//                  stream whole in one work-item, 256 threads, XCD remap
+//                  stream whole in one work-item, 512 threads whose waves
+//                  pass a barrier per row (1.31 ms against 1.52 ms for the
+//                  same grid running free), XCD remap
 //   f32/u32        4 streams/lane, ~4 waves per SIMD, 512 threads, no remap
-//   exponential    2 streams/lane, ~4 waves per SIMD (4 chunks per stream)
-//   normal         2 streams/lane, ~8 waves per SIMD (flat from 2 to 16)
+//                  (VALU-bound: the per-row barrier costs ~5%)
+//   exponential    2 streams/lane, ~4 waves per SIMD (2 chunks per stream),
+//                  256 threads, XCD remap
+//   normal         2 streams/lane, ~8 waves per SIMD (flat from 2 to 16),
+//                  256 threads, XCD remap
 // Non-temporal stores throughout.  Chunks hold at least 96 units; at most
 // 65535 chunks.  A narrower store is used when n_streams or the output
 // alignment does not allow the wide one.
@@ -729,7 +767,8 @@ void plan_generate(GenLaunch& L) {
     if (!L.arith) L.arith = kArithF64;
     const bool spl_auto = !L.spl;
     if (!L.spl) L.spl = plain ? 16 / esz : 2;
-    if (!L.block) L.block = (plain && esz == 4) ? 512 : 256;
+    const bool block_auto = !L.block;
+    if (block_auto) L.block = plain ? 512 : 256;
     if (!cfg_given) {
         L.nontemporal = 1;
         L.xcd = !(plain && esz == 4);
@@ -759,25 +798,37 @@ void plan_generate(GenLaunch& L) {
         nch = (units_max + c - 1) / c;
     }
     L.n_chunks = static_cast<uint32_t>(nch);
+    if (!cfg_given && plain && esz == 8) {
+        // fp64 uniforms are store-bound: once the grid fills the chip (two
+        // waves per SIMD), eight waves per block (one block per CU at the
+        // default size) writing each row together beat free-running waves;
+        // smaller grids are launch-latency-bound and run free in 256-thread
+        // blocks, which start sooner
+        L.lock = n_sblk * nch >= 2048;
+        if (!L.lock && block_auto) L.block = 256;
+    }
     const uint64_t wpb = static_cast<uint64_t>(L.block) / 64;
     const uint64_t gx = (n_sblk + wpb - 1) / wpb;
     if (L.xcd && (gx * nch) % 8) L.xcd = 0;  // the remap needs a multiple of 8 blocks
 }
 
-template <int DIST, int DTYPE, int ARITH, int SPL, bool NT>
+template <int DIST, int DTYPE, int ARITH, int SPL, bool NT, bool LOCK>
 static hipError_t launch_t(const GenLaunch& L, hipStream_t s) {
     const unsigned wpb = static_cast<unsigned>(L.block) / 64;
     const uint64_t ws = 64ull * SPL;
     const uint64_t n_sblk = (static_cast<uint64_t>(L.S) + ws - 1) / ws;
     dim3 grid(static_cast<unsigned>((n_sblk + wpb - 1) / wpb), L.n_chunks);
-    hipLaunchKernelGGL((gen_kernel<DIST, DTYPE, ARITH, SPL, NT>), grid, dim3(L.block), 0, s, L);
+    hipLaunchKernelGGL((gen_kernel<DIST, DTYPE, ARITH, SPL, NT, LOCK>), grid, dim3(L.block), 0, s, L);
     return hipGetLastError();
 }
 
 template <int DIST, int DTYPE, int ARITH, int SPL>
 static hipError_t launch_nt(const GenLaunch& L, hipStream_t s) {
-    return L.nontemporal ? launch_t<DIST, DTYPE, ARITH, SPL, true>(L, s)
-                         : launch_t<DIST, DTYPE, ARITH, SPL, false>(L, s);
+    if (L.nontemporal)
+        return L.lock ? launch_t<DIST, DTYPE, ARITH, SPL, true, true>(L, s)
+                      : launch_t<DIST, DTYPE, ARITH, SPL, true, false>(L, s);
+    return L.lock ? launch_t<DIST, DTYPE, ARITH, SPL, false, true>(L, s)
+                  : launch_t<DIST, DTYPE, ARITH, SPL, false, false>(L, s);
 }
 
 template <int DIST, int DTYPE, int ARITH>

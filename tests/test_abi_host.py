@@ -126,11 +126,45 @@ def test_generate_argument_validation_no_side_effects():
 def test_launch_cfg_validation():
     L = P.lib()
     for cfg in [(100, 0, 0, 0, 0, 0), (256, 0, 2, 0, 0, 0), (256, 0, 0, 3, 0, 0),
-                (256, 0, 0, 0, 3, 0), (256, 0, 0, 0, 8, 0), (256, 0, 0, 0, 0, 2)]:
+                (256, 0, 0, 0, 3, 0), (256, 0, 0, 0, 8, 0), (256, 0, 0, 0, 0, 2),
+                (256, 0, 0, 0, 0, 0, 2)]:
         c = P.mrg_launch_cfg(*cfg)
         st = L.mrg_generate_ex(1, ctypes.c_void_p(256), 4, 10, 0, 0, 1.0, ctypes.c_void_p(256),
                                ctypes.byref(c), None)
         assert st == -1, cfg
+
+
+def test_generate_plan_resolves_the_launch():
+    """The host-side plan: the automatic shape at 2^30 draws over 262,144
+    streams (fp64 uniforms in lockstep blocks of 8 waves, one chunk per
+    stream), free-running waves for the VALU-bound kinds, explicit shapes
+    kept, and the same argument checks as mrg_generate_ex."""
+    S, n = 262144, 262144 * 4096
+    assert P.mrg_generate_plan(S, n) == dict(block=512, chunk=4096, nontemporal=1, arith=2,
+                                             streams_per_lane=2, xcd_remap=1, lockstep=1)
+    for dist, dtype in [(P.MRG_UNIFORM, P.MRG_F32), (P.MRG_RAW, P.MRG_U32), (P.MRG_NORMAL, P.MRG_F64),
+                        (P.MRG_EXPONENTIAL, P.MRG_F64), (P.MRG_EXPONENTIAL, P.MRG_F32)]:
+        p = P.mrg_generate_plan(S, n, dist, dtype)
+        assert p["lockstep"] == 0 and p["nontemporal"] == 1, (dist, dtype, p)
+        units = 4096 // 2 if dist == P.MRG_NORMAL else 4096
+        assert p["chunk"] * -(-units // p["chunk"]) >= units
+    # grids that fill the chip keep lockstep at ragged stream counts (idle
+    # waves pass the barriers); small, latency-bound grids run free
+    for S2, n2 in [(100000, 10 ** 8), (300000, 300000 * 4096 + 17), (131072, 131072 * 4096)]:
+        p = P.mrg_generate_plan(S2, n2)
+        assert p["lockstep"] == 1 and p["block"] == 512 and S2 % p["streams_per_lane"] == 0, (S2, p)
+    for S2, n2 in [(1024, 1024 * 1024), (1000, 1000 * 37 + 5), (1, 1001)]:
+        p = P.mrg_generate_plan(S2, n2)
+        assert p["lockstep"] == 0 and p["block"] == 256, (S2, p)
+    cfg = dict(block=1024, chunk=7, streams_per_lane=4, lockstep=1, nontemporal=0, xcd_remap=0, arith=1)
+    assert P.mrg_generate_plan(1000, 50000, P.MRG_UNIFORM, P.MRG_F32, cfg=cfg) == cfg
+    assert P.mrg_generate_plan(S, n, gen=P.MRG_GEN_MRG31K3P)["arith"] == 0
+    assert set(P.mrg_generate_plan(S, 0).values()) == {0}
+    for args, kw in [((S, n, P.MRG_RAW, P.MRG_F64), {}), ((S, n, P.MRG_EXPONENTIAL, P.MRG_F64, 0.0), {}),
+                     ((0, n), {}), ((S, n), dict(cfg=dict(lockstep=2))), ((1, 1 << 46), {}),
+                     ((S, n), dict(gen=9))]:
+        with pytest.raises(P.MrgError):
+            P.mrg_generate_plan(*args, **kw)
 
 
 def _saved(n, flags=0, gen=1, version=1, magic=b"MRG3", records=None, creator=None, extra=b""):

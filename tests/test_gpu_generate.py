@@ -130,6 +130,26 @@ def test_distributions(cfg, dist, dtype, S, n):
     run_case(rec, n, dist, dtype, 1.0, cfg)
 
 
+LOCK_CFGS = [dict(block=512, streams_per_lane=2, lockstep=1, nontemporal=1, xcd_remap=1),
+             dict(block=512, streams_per_lane=2, lockstep=1, chunk=7),
+             dict(block=256, streams_per_lane=4, lockstep=1, chunk=5, nontemporal=1),
+             dict(block=1024, streams_per_lane=1, lockstep=1, chunk=4),
+             dict(block=1024, streams_per_lane=2, lockstep=1, chunk=16, arith=1)]
+
+
+@pytest.mark.parametrize("cfg", LOCK_CFGS, ids=str)
+@pytest.mark.parametrize("dist,dtype", [(P.MRG_UNIFORM, P.MRG_F64), (P.MRG_UNIFORM, P.MRG_F32),
+                                        (P.MRG_RAW, P.MRG_U32), (P.MRG_NORMAL, P.MRG_F64),
+                                        (P.MRG_EXPONENTIAL, P.MRG_F32)])
+@pytest.mark.parametrize("S,n", [(2048, 2048 * 37 + 1001), (4096, 4096 * 9), (1000, 1000 * 11 + 7)])
+def test_lockstep_blocks(cfg, dist, dtype, S, n):
+    """Blocks whose waves pass a barrier per row (every wave full: S a
+    multiple of the block's streams; otherwise the option is ignored) give
+    the oracle's values, ragged tail and chunk boundaries included."""
+    rec = O.create_streams(GEN, workloads.random_seed(S + 3 * n), S)
+    run_case(rec, n, dist, dtype, 1.0, cfg)
+
+
 @pytest.mark.parametrize("rate", [0.5, 3.0])
 def test_exponential_rate(rate):
     rec = O.create_streams(GEN, workloads.random_seed(5), 64)
