@@ -89,10 +89,12 @@ def pmc_summary(fetch_csv, write_csv, bench_log):
         assert len(ks) == 1, ks
         return d[ks[0]], ks[0]
 
-    is_gen = lambda k: "gen_kernel<0, 0," in k
+    # the fp64-uniform generate kernel that writes the most: the 2^30-draw
+    # launch (the run also has small-grid launches of another instance)
+    gens = [k for k in write if "gen_kernel<0, 0," in k]
+    name = max(gens, key=lambda k: write[k])
     is_copy = lambda k: "copyBuffer" in k
-    g_f, name = pick(fetch, is_gen)
-    g_w, _ = pick(write, is_gen)
+    g_f, g_w = fetch[name], write[name]
     c_f, _ = pick(fetch, is_copy)
     c_w, _ = pick(write, is_copy)
     kib = COPY_PROBE_BYTES / 1024.0
@@ -114,6 +116,29 @@ def measured_traffic():
     with open(TRAFFIC_JSON) as f:
         t = json.load(f)
     return t["bytes_per_launch"] if t.get("source_sha256") == kernel_sha() else None
+
+
+def timed_median(torch, fn, reps=5, inner=3, warm_ms=50.0):
+    """Median over `reps` of the mean time (ms, HIP events on the current
+    stream) of `inner` back-to-back calls, after calls for at least `warm_ms`
+    of wall time, so that a leg that follows an idle GPU is not timed while
+    the clocks are still coming up."""
+    t0 = time.perf_counter()
+    while True:
+        fn()
+        torch.cuda.synchronize()
+        if (time.perf_counter() - t0) * 1e3 >= warm_ms:
+            break
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(inner):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b) / inner)
+    return sorted(ts)[len(ts) // 2]
 
 
 def cpu_baseline(seed):
@@ -327,14 +352,7 @@ def bench_paper(torch, P, workloads, out, reps=5):
     st = P.mrg_streams_create_device(c, S_STREAMS, gen=G)
 
     def timed(fn):
-        fn()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(reps):
-            fn()
-        b.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / reps
+        return timed_median(torch, fn, reps=reps)
 
     ms = timed(lambda: P.mrg_generate(st, N, P.MRG_UNIFORM, P.MRG_F64, out=out, gen=G))
     res = {"mrg31k3p_uniform_f64": {"GSamples_per_s": round(N / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4),
@@ -474,14 +492,7 @@ def main():
         for name, dist, dt, o, esz in [("f32_uniform", P.MRG_UNIFORM, P.MRG_F32, out32, 4),
                                        ("f64_normal", P.MRG_NORMAL, P.MRG_F64, out, 8),
                                        ("f64_exponential", P.MRG_EXPONENTIAL, P.MRG_F64, out, 8)]:
-            P.mrg_generate(streams, N, dist, dt, 1.0, out=o)
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(3):
-                P.mrg_generate(streams, N, dist, dt, 1.0, out=o)
-            b.record()
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b) / 3
+            ms = timed_median(torch, lambda: P.mrg_generate(streams, N, dist, dt, 1.0, out=o))
             var[name] = {"GSamples_per_s": round(N / (ms * 1e-3) / 1e9, 2),
                          "GB_per_s": round(N * esz / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4)}
         del out32
