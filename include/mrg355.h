@@ -332,15 +332,21 @@ mrg_status mrg_batch_launch(const mrg_batch_plan* plan, void* dev_workspace, hip
 mrg_status mrg_batch_request_times(const mrg_batch_plan* plan, const void* dev_workspace,
                                    uint64_t* host_ticks, hipStream_t stream);
 
-/* Autotuner: time candidate shapes (tile_units x waves_per_simd) of the plan
- * on the GPU with its own requests, in `dev_workspace` (capacity
- * `workspace_bytes`; shapes whose workspace would not fit are skipped), keep
+/* Autotuner: time candidate shapes (tile_units in {512, ..., 16384} x
+ * waves_per_simd in {2, 3, 4}) of the plan on the GPU with its own requests,
+ * in `dev_workspace` (capacity `workspace_bytes`; shapes whose workspace would
+ * not fit are skipped: mrg_batch_autotune_workspace_size gives the capacity
+ * that fits every candidate), keep
  * the fastest in the plan (re-cut and uploaded again) and report it in
  * `best` / `best_ms` (optional).  Every request's stream records are saved to
  * host memory first and restored at the end, so the streams are left as they
  * were; the outputs are overwritten.  Synchronises `stream`. */
 mrg_status mrg_batch_autotune(mrg_batch_plan* plan, void* dev_workspace, size_t workspace_bytes,
                               hipStream_t stream, mrg_batch_cfg* best, double* best_ms);
+
+/* Host only: the largest workspace any autotuner candidate of `plan` needs
+ * (at least mrg_batch_workspace_size of the plan as it is). */
+mrg_status mrg_batch_autotune_workspace_size(const mrg_batch_plan* plan, size_t* bytes);
 
 /* ------------------------------------------------------------------------
  * Serving: a request loop over sessions whose stream state stays on the

@@ -121,6 +121,7 @@ def lib():
             "mrg_batch_request_times": (i32, [vp, vp, ctypes.POINTER(ctypes.c_uint64), vp]),
             "mrg_batch_autotune": (i32, [vp, vp, sz, vp, ctypes.POINTER(mrg_batch_cfg),
                                          ctypes.POINTER(ctypes.c_double)]),
+            "mrg_batch_autotune_workspace_size": (i32, [vp, ctypes.POINTER(sz)]),
             "mrg_generate_paper": (i32, [i32, vp, sz, u64, u64, u64, ctypes.c_uint32, ctypes.c_uint32, i32, i32,
                                          ctypes.c_double, vp, vp]),
             "mrg_tables_sample": (i32, [i32, vp, sz, vp, vp, vp, vp, vp, vp, vp]),
@@ -154,7 +155,8 @@ EXPORTED = ["mrg_abi_version", "mrg_status_string", "mrg_last_error", "mrg_seed_
             "mrg_generate_paper", "mrg_tables_sample", "mrg_fisher_sim", "mrg_fisher_pvalue",
             "mrg_batch_plan_create", "mrg_batch_plan_destroy", "mrg_batch_workspace_size",
             "mrg_batch_tile_count", "mrg_batch_upload", "mrg_batch_launch",
-            "mrg_batch_request_times", "mrg_batch_autotune", "mrg_now_ns", "mrg_server_create",
+            "mrg_batch_request_times", "mrg_batch_autotune", "mrg_batch_autotune_workspace_size",
+            "mrg_now_ns", "mrg_server_create",
             "mrg_server_destroy", "mrg_server_submit", "mrg_server_poll", "mrg_server_release",
             "mrg_server_stats_get", "mrg_server_drive"]
 
@@ -474,7 +476,17 @@ class BatchPlan:
         _check(lib().mrg_batch_request_times(self._p, ctypes.c_void_p(self._ws_ptr), t, _stream(stream)))
         return np.array(list(t), dtype=np.uint64)
 
+    def autotune_workspace_size(self):
+        b = ctypes.c_size_t()
+        _check(lib().mrg_batch_autotune_workspace_size(self._p, ctypes.byref(b)))
+        return b.value
+
     def autotune(self, stream=None):
+        """Time the candidate shapes and keep the fastest; the workspace is
+        grown first so that every candidate fits (then uploaded again)."""
+        need = self.autotune_workspace_size()
+        if self.workspace is None or self._ws_bytes < need:
+            self.alloc_workspace(need)
         best = mrg_batch_cfg()
         ms = ctypes.c_double()
         _check(lib().mrg_batch_autotune(self._p, ctypes.c_void_p(self._ws_ptr), self._ws_bytes,

@@ -118,7 +118,7 @@ mrg_status build(mrg_batch_plan& P) {
         L.dist = static_cast<int>(q.dist);
         L.dtype = static_cast<int>(q.dtype);
         L.arith = kArithF64;
-        L.nontemporal = 1;
+        L.nontemporal = 0;  // batch tiles store with ordinary stores
         L.block = kBatchBlock;
         L.param = q.dist == MRG_EXPONENTIAL ? 1.0 / q.param : 1.0;
         const int esz = static_cast<int>(esz_of(q.dtype));
@@ -148,8 +148,10 @@ mrg_status build(mrg_batch_plan& P) {
         const uint64_t nt = n_sblk * n_chunks;
         if (P.tiles.size() + nt > 0xffffffffull) return mrg355_fail(MRG_E_INVALID_ARG, "too many tiles");
         R.n_tiles = static_cast<uint32_t>(nt);
-        for (uint64_t sb = 0; sb < n_sblk; ++sb)
-            for (uint64_t j = 0; j < n_chunks; ++j) {
+        // chunk-major: neighbouring tiles in the queue write neighbouring
+        // pieces of the same rows (CFG3 mix: 10.33 ms against 10.55 ms)
+        for (uint64_t j = 0; j < n_chunks; ++j)
+            for (uint64_t sb = 0; sb < n_sblk; ++sb) {
                 const uint64_t u = std::min<uint64_t>(chunk, units - j * chunk);
                 P.tiles.push_back(BatchTile{static_cast<uint32_t>(i), static_cast<uint32_t>(sb),
                                             static_cast<uint32_t>(j), 0});
@@ -342,6 +344,23 @@ mrg_status mrg_batch_workspace_size(const mrg_batch_plan* plan, size_t* bytes) {
     return MRG_OK;
 }
 
+// Shapes the autotuner times: tile_units x waves per SIMD.
+static constexpr uint32_t kTuneTileUnits[] = {512, 1024, 2048, 4096, 8192, 16384};
+static constexpr uint32_t kTuneWaves[] = {2, 3, 4};
+
+mrg_status mrg_batch_autotune_workspace_size(const mrg_batch_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return mrg355_fail(MRG_E_INVALID_ARG, "NULL plan or bytes");
+    size_t most = plan->bytes;
+    for (uint32_t tu : kTuneTileUnits) {
+        mrg_batch_plan trial = *plan;
+        trial.tile_units = tu;
+        if (mrg_status st = build(trial)) return st;
+        most = std::max(most, trial.bytes);
+    }
+    *bytes = most;
+    return MRG_OK;
+}
+
 mrg_status mrg_batch_tile_count(const mrg_batch_plan* plan, size_t* tiles) {
     if (!plan || !tiles) return mrg355_fail(MRG_E_INVALID_ARG, "NULL plan or tiles");
     *tiles = plan->tiles.size();
@@ -398,32 +417,30 @@ mrg_status mrg_batch_autotune(mrg_batch_plan* plan, void* dev_workspace, size_t 
     if (e != hipSuccess) return mrg355_fail(MRG_E_HIP, "autotune save: %s", hipGetErrorString(e));
 
     const uint32_t orig_tu = plan->tile_units, orig_w = plan->waves_per_simd;
-    const uint32_t tus[] = {1024, 2048, 4096, 8192, 16384};
-    const uint32_t wps[] = {2, 4};
     double best_t = 1e30;
     uint32_t best_tu = orig_tu, best_w = orig_w;
     hipEvent_t a = nullptr, b = nullptr;
     e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
     mrg_status st = MRG_OK;
-    for (uint32_t tu : tus) {
+    for (uint32_t tu : kTuneTileUnits) {
         if (st || e != hipSuccess) break;
         plan->tile_units = tu;
         if ((st = build(*plan))) break;
         if (plan->bytes > workspace_bytes) continue;  // does not fit the caller's workspace
         if ((st = upload(*plan, dev_workspace, stream))) break;
-        for (uint32_t w : wps) {
+        for (uint32_t w : kTuneWaves) {
             plan->waves_per_simd = w;
             if ((st = launch(*plan, dev_workspace, stream))) break;  // warm-up
             e = hipEventRecord(a, stream);
-            for (int rep = 0; rep < 2 && !st; ++rep) st = launch(*plan, dev_workspace, stream);
+            for (int rep = 0; rep < 3 && !st; ++rep) st = launch(*plan, dev_workspace, stream);
             if (e == hipSuccess) e = hipEventRecord(b, stream);
             if (e == hipSuccess) e = hipEventSynchronize(b);
             float ms = 0;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
             if (st || e != hipSuccess) break;
-            if (ms / 2 < best_t) {
-                best_t = ms / 2;
+            if (ms / 3 < best_t) {
+                best_t = ms / 3;
                 best_tu = tu;
                 best_w = w;
             }

@@ -424,18 +424,22 @@ __global__ void __launch_bounds__(256) batch_init_kernel(BatchLaunch B) {
     }
 }
 
+// Batch tiles use ordinary stores: requests of a few hundred streams have rows
+// that seldom start on a 128-byte line, and L2 then merges the halves of the
+// line two neighbouring tiles share (CFG3 mix: 9.97 ms against 10.30 ms with
+// non-temporal stores; f32 uniforms 1.34 against 1.71 ms).
 template <int KIND>
 __device__ __forceinline__ void batch_tile(const GenLaunch& L, uint32_t sblk, uint32_t chunk) {
-    if constexpr (KIND == kBUniF64x1) run_chunk<kUniform, kF64, kArithF64, 1, true>(L, sblk, chunk);
-    if constexpr (KIND == kBUniF64x2) run_chunk<kUniform, kF64, kArithF64, 2, true>(L, sblk, chunk);
-    if constexpr (KIND == kBUniF32x1) run_chunk<kUniform, kF32, kArithF64, 1, true>(L, sblk, chunk);
-    if constexpr (KIND == kBUniF32x4) run_chunk<kUniform, kF32, kArithF64, 4, true>(L, sblk, chunk);
-    if constexpr (KIND == kBRawU32x1) run_chunk<kRaw, kU32, kArithF64, 1, true>(L, sblk, chunk);
-    if constexpr (KIND == kBRawU32x4) run_chunk<kRaw, kU32, kArithF64, 4, true>(L, sblk, chunk);
-    if constexpr (KIND == kBNormF64) run_chunk<kNormal, kF64, kArithF64, 1, true>(L, sblk, chunk);
-    if constexpr (KIND == kBNormF32) run_chunk<kNormal, kF32, kArithF64, 1, true>(L, sblk, chunk);
-    if constexpr (KIND == kBExpF64) run_chunk<kExponential, kF64, kArithF64, 1, true>(L, sblk, chunk);
-    if constexpr (KIND == kBExpF32) run_chunk<kExponential, kF32, kArithF64, 1, true>(L, sblk, chunk);
+    if constexpr (KIND == kBUniF64x1) run_chunk<kUniform, kF64, kArithF64, 1, false>(L, sblk, chunk);
+    if constexpr (KIND == kBUniF64x2) run_chunk<kUniform, kF64, kArithF64, 2, false>(L, sblk, chunk);
+    if constexpr (KIND == kBUniF32x1) run_chunk<kUniform, kF32, kArithF64, 1, false>(L, sblk, chunk);
+    if constexpr (KIND == kBUniF32x4) run_chunk<kUniform, kF32, kArithF64, 4, false>(L, sblk, chunk);
+    if constexpr (KIND == kBRawU32x1) run_chunk<kRaw, kU32, kArithF64, 1, false>(L, sblk, chunk);
+    if constexpr (KIND == kBRawU32x4) run_chunk<kRaw, kU32, kArithF64, 4, false>(L, sblk, chunk);
+    if constexpr (KIND == kBNormF64) run_chunk<kNormal, kF64, kArithF64, 1, false>(L, sblk, chunk);
+    if constexpr (KIND == kBNormF32) run_chunk<kNormal, kF32, kArithF64, 1, false>(L, sblk, chunk);
+    if constexpr (KIND == kBExpF64) run_chunk<kExponential, kF64, kArithF64, 1, false>(L, sblk, chunk);
+    if constexpr (KIND == kBExpF32) run_chunk<kExponential, kF32, kArithF64, 1, false>(L, sblk, chunk);
 }
 
 // Persistent kernel.  Tiles come in three classes with separate queues:
@@ -770,7 +774,11 @@ void plan_generate(GenLaunch& L) {
     const bool block_auto = !L.block;
     if (block_auto) L.block = plain ? 512 : 256;
     if (!cfg_given) {
-        L.nontemporal = 1;
+        // Non-temporal stores when rows start on 128-byte lines; otherwise
+        // the line a wave shares with its neighbour is written in two halves,
+        // which L2 merges only when it keeps them (2^30 fp64 uniforms over
+        // 262,143 streams: 2.13 ms with nt stores, 1.80 ms without)
+        L.nontemporal = (static_cast<uint64_t>(L.S) * esz) % 128 == 0;
         L.xcd = !(plain && esz == 4);
     }
     // at most 16 bytes per store; narrower when the shape does not allow it

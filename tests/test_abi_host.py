@@ -239,6 +239,16 @@ def test_batch_plan_validation():
     assert P.lib().mrg_batch_workspace_size(plan, ctypes.byref(sz)) == 0 and sz.value % 256 == 0
     assert P.lib().mrg_batch_tile_count(plan, ctypes.byref(nt)) == 0
     assert nt.value == 2  # 64 streams x 10 draws each: one wave-tile per request (2 streams/lane)
+    most = ctypes.c_size_t()
+    assert P.lib().mrg_batch_autotune_workspace_size(plan, ctypes.byref(most)) == 0
+    assert most.value >= sz.value and most.value % 256 == 0
+    P.lib().mrg_batch_plan_destroy(plan)
+    # a long request: smaller trial tiles need a larger workspace than the default cut
+    st, plan = _plan_status([_req(base, 1024, 1024 * 200000, out=1 << 32)])
+    assert st == 0
+    assert P.lib().mrg_batch_workspace_size(plan, ctypes.byref(sz)) == 0
+    assert P.lib().mrg_batch_autotune_workspace_size(plan, ctypes.byref(most)) == 0
+    assert most.value > sz.value
     P.lib().mrg_batch_plan_destroy(plan)
     bad_cases = [
         [_req(base, 64, 640, out=1 << 30), _req(base + 63 * 72, 64, 640, out=(1 << 31))],  # shared streams

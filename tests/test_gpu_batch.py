@@ -181,14 +181,16 @@ def test_batch_graph_replay_matches_eager():
 
 def test_batch_autotune_leaves_streams_and_stays_exact():
     A, B = Mix(MIX, 4), Mix(MIX, 4)
-    small = P.BatchPlan(A.requests(), dict(tile_units=1024))
-    nbytes = small.workspace_size()
+    small = P.BatchPlan(A.requests(), dict(tile_units=512))
     plan = P.BatchPlan(A.requests())
-    plan.alloc_workspace(max(nbytes, plan.workspace_size()))
+    assert plan.autotune_workspace_size() >= small.workspace_size()
+    plan.alloc_workspace()  # the default cut's size: autotune grows it for the smaller trial tiles
     plan.upload()
     before = [t.clone() for t in A.streams]
     best, ms = plan.autotune()
-    assert best["tile_units"] in (1024, 2048, 4096, 8192, 16384) and best["waves_per_simd"] in (2, 4) and ms > 0
+    assert plan.workspace_size() <= plan._ws_bytes
+    assert best["tile_units"] in (512, 1024, 2048, 4096, 8192, 16384) and best["waves_per_simd"] in (2, 3, 4)
+    assert ms > 0
     for a, b in zip(A.streams, before):
         assert torch.equal(a, b)
     plan.launch()
