@@ -150,6 +150,18 @@ def test_lockstep_blocks(cfg, dist, dtype, S, n):
     run_case(rec, n, dist, dtype, 1.0, cfg)
 
 
+@pytest.mark.parametrize("S,n", [(100003, 100003 * 130 + 77), (100000, 100000 * 500 + 99999), (65536, 65536 * 300)])
+def test_default_plan_lockstep_at_scale(S, n):
+    """Automatic launches large enough for lockstep blocks: ragged stream
+    counts (the last block's spare waves only pass the barriers), odd S (one
+    stream per lane, rows off 128-byte lines, ordinary stores) and a ragged
+    tail; every value and state against the oracle."""
+    plan = P.mrg_generate_plan(S, n)
+    assert plan["lockstep"] == 1, plan
+    rec = O.create_streams(GEN, workloads.random_seed(S), S)
+    run_case(rec, n, P.MRG_UNIFORM, P.MRG_F64)
+
+
 @pytest.mark.parametrize("rate", [0.5, 3.0])
 def test_exponential_rate(rate):
     rec = O.create_streams(GEN, workloads.random_seed(5), 64)
