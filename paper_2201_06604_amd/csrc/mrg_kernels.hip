@@ -103,7 +103,7 @@ __device__ __forceinline__ typename ElemOf<DTYPE>::T value1(Z z, double inv_rate
 template <int G, typename Z>
 __device__ __forceinline__ void box_muller(Z z1, Z z2, double& x, double& y) {
     double u1 = to_f64(z1) * norm_of<G>(), u2 = to_f64(z2) * norm_of<G>();
-    double r = sqrt(-2.0 * log_unit(u1));
+    double r = sqrt_radius(-2.0 * log_unit(u1));
     double s, c;
     sincospi_unit(2.0 * u2, &s, &c);
     x = r * c;
