@@ -266,7 +266,12 @@ __device__ __forceinline__ double sqrt_radius(double x) {
 // which leaves an error of order 1e-29 before rounding; a second Newton step
 // changed no result over all inputs of either generator.  Accuracy is checked
 // against the library log over every uniform the generators can produce.
+// SCALE (1, -1, 2 or -2) multiplies the result: it is folded into the last
+// three steps' constants, and scaling by a power of two commutes with
+// rounding, so log_unit<SCALE>(u) is bit for bit SCALE * log_unit(u).
+template <int SCALE = 1>
 __device__ __forceinline__ double log_unit(double u) {
+    static_assert(SCALE == 1 || SCALE == -1 || SCALE == 2 || SCALE == -2, "power-of-two scale");
     int k = __builtin_amdgcn_frexp_exp(u);          // u = mant * 2^k, mant in [1/2, 1)
     double m = __builtin_amdgcn_frexp_mant(u);
     if (m < 0.70710678118654752440) {
@@ -291,12 +296,12 @@ __device__ __forceinline__ double log_unit(double u) {
     r = __builtin_fma(r, z, 1.0 / 5.0);
     r = __builtin_fma(r, z, 1.0 / 3.0);
     r = r * z;
-    const double s2 = q + q;
+    const double s2 = q * (2.0 * SCALE);
     const double log_m = __builtin_fma(s2, r, s2);
     const double kd = static_cast<double>(k);
     constexpr double kLn2Hi = 6.93147180369123816490e-01;  // ln 2 to 32 bits: k * hi exact for |k| < 2^20
     constexpr double kLn2Lo = 1.90821492927058770002e-10;  // ln 2 - hi
-    return __builtin_fma(kd, kLn2Hi, __builtin_fma(kd, kLn2Lo, log_m));
+    return __builtin_fma(kd, kLn2Hi * SCALE, __builtin_fma(kd, kLn2Lo * SCALE, log_m));
 }
 
 __device__ __forceinline__ double to_f64(uint32_t z) { return static_cast<double>(z); }

@@ -100,12 +100,15 @@ __device__ __forceinline__ typename ElemOf<DTYPE>::T value1(Z z, double inv_rate
 }
 
 // Box-Muller pair (Algorithm 1) from two consecutive steps of one stream.
+// The factors -2 and 2 are folded into exact power-of-two scalings: -2 log(u1)
+// comes from log_unit<-2>, and 2 u2 = z2 (2 NORM) is the same double as
+// 2 (z2 NORM).
 template <int G, typename Z>
 __device__ __forceinline__ void box_muller(Z z1, Z z2, double& x, double& y) {
-    double u1 = to_f64(z1) * norm_of<G>(), u2 = to_f64(z2) * norm_of<G>();
-    double r = sqrt_radius(-2.0 * log_unit(u1));
+    const double u1 = to_f64(z1) * norm_of<G>();
+    const double r = sqrt_radius(log_unit<-2>(u1));
     double s, c;
-    sincospi_unit(2.0 * u2, &s, &c);
+    sincospi_unit(to_f64(z2) * (2.0 * norm_of<G>()), &s, &c);
     x = r * c;
     y = r * s;
 }
