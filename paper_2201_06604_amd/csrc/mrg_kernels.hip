@@ -62,12 +62,13 @@ __device__ __forceinline__ void dev_jump(uint32_t x[6], uint64_t e) {
         if (e & 1) dev_apply<G>(dev_tab<G>().step_pow2[0][b], dev_tab<G>().step_pow2[1][b], x);
 }
 
-// Largest float <= u for u in [2^-126, 1): drop the low 29 mantissa bits
-// after rebasing the exponent (1023 -> 127).
-__device__ __forceinline__ float f32_rz(double u) {
-    uint64_t b = static_cast<uint64_t>(__double_as_longlong(u));
-    uint64_t r = b - (static_cast<uint64_t>(896) << 52);
-    return __uint_as_float(static_cast<uint32_t>(r >> 29));
+// Largest float <= u (u in [2^-126, 1)) from v = u 2^-896, a normal double
+// whose exponent field is already rebased from the double's bias to the
+// float's (1023 - 127 = 896): the float is v's bits without the low 29
+// mantissa bits.  Callers form v with the scale NORM 2^-896, which rounds
+// exactly as NORM does (a power-of-two factor, no underflow for u >= 2^-126).
+__device__ __forceinline__ float f32_rz_rebased(double v) {
+    return __uint_as_float(static_cast<uint32_t>(static_cast<uint64_t>(__double_as_longlong(v)) >> 29));
 }
 
 template <int DTYPE> struct ElemOf;
@@ -86,6 +87,8 @@ template <int DIST, int DTYPE, int G, typename Z>
 __device__ __forceinline__ typename ElemOf<DTYPE>::T value1(Z z, double inv_rate) {
     if constexpr (DIST == kRaw) {
         return to_u32(z);
+    } else if constexpr (DIST == kUniform && DTYPE == kF32) {
+        return f32_rz_rebased(to_f64(z) * (norm_of<G>() * 0x1p-896));
     } else {
         double u = to_f64(z) * norm_of<G>();
         if constexpr (DIST == kExponential) {
@@ -93,8 +96,7 @@ __device__ __forceinline__ typename ElemOf<DTYPE>::T value1(Z z, double inv_rate
             if constexpr (DTYPE == kF64) return v;
             else return static_cast<float>(v);
         } else {
-            if constexpr (DTYPE == kF64) return u;
-            else return f32_rz(u);
+            return u;
         }
     }
 }
