@@ -43,6 +43,11 @@ MIX = [
     (2, 2 * 9000 + 1, P.MRG_UNIFORM, P.MRG_F64, 1.0),
     (4, 4 * 7001, P.MRG_NORMAL, P.MRG_F64, 1.0),
     (1, 12345, P.MRG_UNIFORM, P.MRG_F32, 1.0),
+    # uniform/raw requests over several workgroup tiles per chunk: spare waves
+    # in the last group, odd S (one stream per lane), rows off 128-byte lines
+    (1100, 1100 * 23 + 77, P.MRG_UNIFORM, P.MRG_F64, 1.0),
+    (1031, 1031 * 11 + 3, P.MRG_UNIFORM, P.MRG_F32, 1.0),
+    (520, 520 * 40, P.MRG_RAW, P.MRG_U32, 1.0),
 ]
 
 
