@@ -431,7 +431,7 @@ __global__ void __launch_bounds__(256) batch_init_kernel(BatchLaunch B) {
 
 // Batch tiles use ordinary stores: requests of a few hundred streams have rows
 // that seldom start on a 128-byte line, and L2 then merges the halves of the
-// line two neighbouring tiles share (CFG3 mix: 9.97 ms against 10.30 ms with
+// line two neighbouring tiles share (4,096-request mix: 9.97 ms against 10.30 ms with
 // non-temporal stores; f32 uniforms 1.34 against 1.71 ms).
 template <int KIND>
 __device__ __forceinline__ void batch_tile(const GenLaunch& L, uint32_t sblk, uint32_t chunk) {
