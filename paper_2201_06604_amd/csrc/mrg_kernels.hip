@@ -766,8 +766,8 @@ hipError_t launch_advance(int gen, uint32_t* streams, uint64_t n, uint64_t steps
 //                  256 threads, XCD remap
 //   normal         2 streams/lane, ~8 waves per SIMD (flat from 2 to 16),
 //                  256 threads, XCD remap
-// Non-temporal stores throughout.  Chunks hold at least 96 units; at most
-// 65535 chunks.  A narrower store is used when n_streams or the output
+// Chunks hold at least 96 units (32 with one stream per lane on grids below
+// two waves per SIMD); at most 65535 chunks.  A narrower store is used when n_streams or the output
 // alignment does not allow the wide one.
 void plan_generate(GenLaunch& L) {
     const int esz = L.dtype == kF64 ? 8 : 4;
@@ -793,16 +793,29 @@ void plan_generate(GenLaunch& L) {
         while (L.spl > 1 && 64ull * L.spl > L.S) L.spl /= 2;
     const uint64_t cnt_max = L.q + (L.r ? 1 : 0);
     const uint64_t units_max = L.dist == kNormal ? (cnt_max + 1) / 2 : cnt_max;
-    const uint64_t ws = 64ull * L.spl;
-    const uint64_t n_sblk = (static_cast<uint64_t>(L.S) + ws - 1) / ws;
-    if (!L.chunk) {
-        const uint64_t target_waves = L.dist == kNormal ? 8192 : (L.dist == kExponential ? 4096 : (esz == 8 ? 2048 : 4096));
+    const uint64_t target_waves = L.dist == kNormal ? 8192 : (L.dist == kExponential ? 4096 : (esz == 8 ? 2048 : 4096));
+    // chunk for about target_waves waves, at least min_units units each
+    auto auto_chunk = [&](uint64_t n_sblk, uint64_t min_units) {
         uint64_t w = (target_waves + n_sblk - 1) / n_sblk;
-        uint64_t w_cap = (units_max + 95) / 96;
+        const uint64_t w_cap = (units_max + min_units - 1) / min_units;
         if (w > w_cap) w = w_cap;
         if (w < 1) w = 1;
-        uint64_t c = (units_max + w - 1) / w;
-        L.chunk = static_cast<uint32_t>(c > 0xffffffffull ? 0xffffffffull : (c ? c : 1));
+        const uint64_t c = (units_max + w - 1) / w;
+        return static_cast<uint32_t>(c > 0xffffffffull ? 0xffffffffull : (c ? c : 1));
+    };
+    uint64_t n_sblk = (static_cast<uint64_t>(L.S) + 64ull * L.spl - 1) / (64ull * L.spl);
+    if (!L.chunk) {
+        L.chunk = auto_chunk(n_sblk, 96);
+        const uint64_t waves = n_sblk * (units_max ? (units_max + L.chunk - 1) / L.chunk : 0);
+        if (!cfg_given && waves < 2048) {
+            // A grid below two waves per SIMD is launch-latency-bound: more,
+            // shorter waves finish sooner (1,024 streams x 1,024 fp64
+            // uniforms: 36 us at two streams per lane and 96-draw chunks,
+            // 25 us at one stream per lane and 32-64-draw chunks)
+            L.spl = 1;
+            n_sblk = (static_cast<uint64_t>(L.S) + 63) / 64;
+            L.chunk = auto_chunk(n_sblk, 32);
+        }
     }
     uint64_t nch = units_max ? (units_max + L.chunk - 1) / L.chunk : 0;
     if (nch > 65535) {
