@@ -900,16 +900,17 @@ int batch_kind(int dist, int dtype, int spl) {
     }
 }
 
-// Blocks of the persistent batch kernel that fit on one CU at once.
+// Blocks of the persistent batch kernel that fit on one CU at once (a
+// property of the compiled kernel; computed once, thread-safely).
 int batch_blocks_per_cu() {
-    static int cached = 0;
-    if (cached) return cached;
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(batch_kernel), 256, 0) !=
-            hipSuccess || n <= 0)
-        n = 1;
-    cached = n;
-    return n;
+    static const int cached = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(batch_kernel), 256, 0) !=
+                hipSuccess || n <= 0)
+            n = 1;
+        return n;
+    }();
+    return cached;
 }
 
 int device_cu_count() {
