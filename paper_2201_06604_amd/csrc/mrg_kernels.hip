@@ -35,12 +35,20 @@ __constant__ JumpTables g_tab = make_jump_tables<kGen32k3a>();
 __constant__ JumpTables g_tab31 = make_jump_tables<kGen31k3p>();
 static constexpr JumpTables kHostTab = make_jump_tables<kGen32k3a>();
 static constexpr JumpTables kHostTab31 = make_jump_tables<kGen31k3p>();
+__constant__ StreamDigits g_dig = make_stream_digits<kGen32k3a>(kHostTab);
+__constant__ StreamDigits g_dig31 = make_stream_digits<kGen31k3p>(kHostTab31);
 
 // ------------------------------------------------------------------ jumps
 template <int G>
 __device__ __forceinline__ const JumpTables& dev_tab() {
     if constexpr (G == kGen32k3a) return g_tab;
     else return g_tab31;
+}
+
+template <int G>
+__device__ __forceinline__ const StreamDigits& dev_dig() {
+    if constexpr (G == kGen32k3a) return g_dig;
+    else return g_dig31;
 }
 
 // x <- (M1 x[0..2], M2 x[3..5]) modulo the generator's two moduli.
@@ -581,10 +589,11 @@ __global__ void __launch_bounds__(256) batch_finalize_kernel(BatchLaunch B) {
 // ------------------------------------------------------ stream creation
 // Stream i = J^i creator with J = A^Z (Z = 2^127, or 2^134 for MRG31k3p),
 // in two passes: create_starts_kernel computes stream 64w (the first stream
-// of each group of 64) from the bits of 64w, and create_lanes_kernel takes
-// stream 64w + l to J^l times it (the 6 low bits).  The long chain of
-// matrix-vector products is done once per 64 streams instead of per stream.
-// The per-bit tables are read with wave-uniform indices (scalar loads).
+// of each group of 64), and create_lanes_kernel takes stream 64w + l to J^l
+// times it.  J^i is the product of one table entry per nonzero base-64 digit
+// of i (StreamDigits: J^(v 64^d)), so a lane makes at most one matrix-vector
+// product per digit: one in create_lanes_kernel, at most five in
+// create_starts_kernel (i < 2^36).
 template <int G>
 __device__ __forceinline__ void write_record(uint32_t* rec, const uint32_t x[6]) {
 #pragma unroll
@@ -595,18 +604,16 @@ __device__ __forceinline__ void write_record(uint32_t* rec, const uint32_t x[6])
     }
 }
 
-// Copy jump matrices [first, first + count) of both components into LDS as
-// doubles (one burst of independent loads per block instead of a scalar load
-// per step of a lane's serial chain); creation then multiplies in fp64
-// (matvec_f64: the same integers as the 64-bit integer products, with a
-// third of the instructions).
+// Copy digit tables [first, first + count) of both components into LDS as
+// doubles (each lane picks its own entry, so they cannot be scalar loads);
+// creation then multiplies in fp64 (matvec_f64: the same integers as the
+// 64-bit integer products, with a third of the instructions).
 template <int G>
-__device__ __forceinline__ void stage_stream_tables(double (*dst)[2][9], int first, int count) {
-    const uint32_t* src0 = dev_tab<G>().stream_pow2[0][first].a;
-    const uint32_t* src1 = dev_tab<G>().stream_pow2[1][first].a;
-    for (int k = threadIdx.x; k < count * 9; k += blockDim.x) {
-        dst[k / 9][0][k % 9] = static_cast<double>(src0[k]);
-        dst[k / 9][1][k % 9] = static_cast<double>(src1[k]);
+__device__ __forceinline__ void stage_digit_tables(double (*dst)[64][2][9], int first, int count) {
+    for (int k = threadIdx.x; k < count * 64 * 9; k += blockDim.x) {
+        const int d = k / (64 * 9), v = (k / 9) % 64, e = k % 9;
+        dst[d][v][0][e] = static_cast<double>(dev_dig<G>().digit[first + d][0][v].a[e]);
+        dst[d][v][1][e] = static_cast<double>(dev_dig<G>().digit[first + d][1][v].a[e]);
     }
     __syncthreads();
 }
@@ -619,18 +626,22 @@ __device__ __forceinline__ void apply_f64(const double (&M)[2][9], double x[6]) 
     matvec_f64(M[1], x + 3, m2, 1.0 / m2);
 }
 
+// Stream 64 g for the group index g < 2^30: digit d of g is digit d + 1 of
+// the stream index.  ndig = base-64 digits of the largest group index.
 template <int G>
 __global__ void __launch_bounds__(256) create_starts_kernel(uint32_t* out, uint64_t n_groups, uint32_t c0,
                                                             uint32_t c1, uint32_t c2, uint32_t c3, uint32_t c4,
-                                                            uint32_t c5, int nbits) {
-    __shared__ double tab[58][2][9];  // J^(2^(b+6)), b < nbits <= 58
-    stage_stream_tables<G>(tab, 6, nbits);
+                                                            uint32_t c5, int ndig) {
+    __shared__ double tab[kStreamDigits - 1][64][2][9];  // J^(v 64^(d+1)), d < ndig <= 5
+    stage_digit_tables<G>(tab, 1, ndig);
     const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= n_groups) return;
     double x[6] = {static_cast<double>(c0), static_cast<double>(c1), static_cast<double>(c2),
                    static_cast<double>(c3), static_cast<double>(c4), static_cast<double>(c5)};
-    for (int b = 0; b < nbits; ++b)  // stream index 64 g: bit b of g is bit b + 6
-        if ((g >> b) & 1) apply_f64<G>(tab[b], x);
+    for (int d = 0; d < ndig; ++d) {  // uniform loop; the digit is the lane's own
+        const uint32_t v = static_cast<uint32_t>(g >> (6 * d)) & 63u;
+        if (v) apply_f64<G>(tab[d][v], x);
+    }
     uint32_t w[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) w[k] = static_cast<uint32_t>(x[k]);
@@ -641,9 +652,9 @@ __global__ void __launch_bounds__(256) create_starts_kernel(uint32_t* out, uint6
 // and written with coalesced dword stores.
 template <int G>
 __global__ void __launch_bounds__(256) create_lanes_kernel(uint32_t* out, uint64_t n) {
-    __shared__ double tab[6][2][9];  // J^(2^b), b < 6
+    __shared__ double tab[1][64][2][9];  // J^v, v < 64
     __shared__ uint32_t recs[256 * 18];
-    stage_stream_tables<G>(tab, 0, 6);
+    stage_digit_tables<G>(tab, 0, 1);
     const uint64_t first_i = static_cast<uint64_t>(blockIdx.x) * 256;
     const uint64_t i = first_i + threadIdx.x;
     if (i < n) {
@@ -651,9 +662,8 @@ __global__ void __launch_bounds__(256) create_lanes_kernel(uint32_t* out, uint64
         double x[6];
 #pragma unroll
         for (int w = 0; w < 6; ++w) x[w] = static_cast<double>(start[w]);
-#pragma unroll
-        for (int b = 0; b < 6; ++b)
-            if ((i >> b) & 1) apply_f64<G>(tab[b], x);
+        const uint32_t v = static_cast<uint32_t>(i) & 63u;
+        if (v) apply_f64<G>(tab[0][v], x);
         uint32_t w[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) w[k] = static_cast<uint32_t>(x[k]);
@@ -724,10 +734,11 @@ static unsigned grid1d(uint64_t n, unsigned block) {
 template <int G>
 static hipError_t launch_create_t(uint32_t* out, uint64_t n, const uint32_t c[6], hipStream_t s) {
     const uint64_t groups = (n + 63) / 64;
-    int nbits = 0;  // bits of the largest group index
-    while (nbits < 58 && ((groups - 1) >> nbits)) ++nbits;
+    int ndig = 0;  // base-64 digits of the largest group index
+    while (ndig < kStreamDigits && ((groups - 1) >> (6 * ndig))) ++ndig;
+    if (ndig > kStreamDigits - 1) return hipErrorInvalidValue;  // more than 2^36 streams (refused by the API)
     hipLaunchKernelGGL(create_starts_kernel<G>, dim3(grid1d(groups, 256)), dim3(256), 0, s, out, groups, c[0], c[1],
-                       c[2], c[3], c[4], c[5], nbits);
+                       c[2], c[3], c[4], c[5], ndig);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || n == 1) return e;
     hipLaunchKernelGGL(create_lanes_kernel<G>, dim3(grid1d(n, 256)), dim3(256), 0, s, out, n);

@@ -226,4 +226,31 @@ MRG_HD constexpr JumpTables make_jump_tables() {
     return T;
 }
 
+// Stream jumps by base-64 digits: digit[d][j][v] = J^(v 64^d) for component
+// j (J = the jump between neighbouring streams, A^(2^127) or A^(2^134)), so
+// J^i for a stream index i < 2^36 is the product of at most six entries, one
+// per nonzero base-64 digit of i (powers of one matrix commute).
+constexpr int kStreamDigits = 6;
+struct StreamDigits {
+    Mat3 digit[kStreamDigits][2][64];
+};
+
+template <int G>
+MRG_HD constexpr StreamDigits make_stream_digits(const JumpTables& T) {
+    constexpr int B = G == kGen32k3a ? 32 : 31;
+    StreamDigits D{};
+    for (int j = 0; j < 2; ++j) {
+        const uint32_t c = G == kGen32k3a ? comp_c(j) : comp_c31(j);
+        for (int d = 0; d < kStreamDigits; ++d) {
+            const Mat3& base = T.stream_pow2[j][6 * d];  // J^(64^d)
+            Mat3 P = identity();
+            for (int v = 0; v < 64; ++v) {
+                D.digit[d][j][v] = P;
+                P = matmul<B>(P, base, c);
+            }
+        }
+    }
+    return D;
+}
+
 }  // namespace mrg355
