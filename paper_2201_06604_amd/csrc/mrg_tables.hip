@@ -77,20 +77,15 @@ struct GenOf<kGen31k3p> {
     static constexpr double norm = kNorm31;
 };
 
-// Tables t < n: shape I[t] x J[t] (<= 5 x 5), margins rows[t][5], cols[t][5],
+// Table t: shape I[t] x J[t] (<= 5 x 5), margins rows[t][5], cols[t][5],
 // from stream t; outputs tabs[t][5][5] (zero padded) and stats[t] (optional).
 // A table whose shape is out of range or whose margins are negative, differ
 // in total or total more than kTableMaxTotal gets zeros and a NaN statistic,
 // and its stream is left as it was (the checks also bound every loop).
 template <int G>
-__global__ void __launch_bounds__(kTableBlock) tables_kernel(uint32_t* streams, uint64_t n, const int32_t* I,
-                                                             const int32_t* J, const int32_t* rows, const int32_t* cols,
-                                                             int32_t* tabs, double* stats) {
-    __shared__ double ck_s[kCk * kTableBlock], ck_w[kCk * kTableBlock];
-    __shared__ int ck_r[kCk * kTableBlock];
-    const HyperCk ck{ck_s + threadIdx.x, ck_w + threadIdx.x, ck_r + threadIdx.x, kTableBlock};
-    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= n) return;
+__device__ __forceinline__ void one_table(uint64_t t, uint32_t* streams, const int32_t* I, const int32_t* J,
+                                          const int32_t* rows, const int32_t* cols, int32_t* tabs, double* stats,
+                                          const HyperCk& ck) {
     int32_t* out = tabs + t * 25;
 #pragma unroll
     for (int k = 0; k < 25; ++k) out[k] = 0;
@@ -121,6 +116,52 @@ __global__ void __launch_bounds__(kTableBlock) tables_kernel(uint32_t* streams, 
     e.save(x);
 #pragma unroll
     for (int w = 0; w < 6; ++w) rec[w] = x[w];
+}
+
+// A block takes 256 consecutive tables.  A table makes (I-1)(J-1)
+// inversions, 1 to 16, each searching a range that grows like the square
+// root of the table's total, and a wave runs as long as its longest lane;
+// so the block first orders its tables by the estimate (I-1)(J-1) sqrt(total)
+// in 64 buckets (a counting sort in LDS: the order within a bucket does not
+// matter, every table has its own stream and output), and each wave then
+// takes 64 tables of about the same work (10^6 tables of the 2x2..5x5 mix:
+// 2.62 -> 2.40 ms).  Sorting windows of 3 or 7 blocks' tables, taken in
+// rounds by fewer blocks, were no faster or slower.
+template <int G>
+__global__ void __launch_bounds__(kTableBlock) tables_kernel(uint32_t* streams, uint64_t n, const int32_t* I,
+                                                             const int32_t* J, const int32_t* rows, const int32_t* cols,
+                                                             int32_t* tabs, double* stats) {
+    __shared__ double ck_s[kCk * kTableBlock], ck_w[kCk * kTableBlock];
+    __shared__ int ck_r[kCk * kTableBlock];
+    constexpr int kBuckets = 64;
+    __shared__ uint16_t order[kTableBlock];
+    __shared__ uint32_t start[kBuckets + 1];
+    const HyperCk ck{ck_s + threadIdx.x, ck_w + threadIdx.x, ck_r + threadIdx.x, kTableBlock};
+    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kTableBlock;
+    const uint32_t here = n - base < kTableBlock ? static_cast<uint32_t>(n - base) : kTableBlock;
+    // bucket of the work estimate (0 for shapes out of range: they stop at once)
+    auto key_of = [&](uint32_t k) {
+        const uint64_t t = base + k;
+        const int It = I[t], Jt = J[t];
+        if (!(It >= 1 && It <= 5 && Jt >= 1 && Jt <= 5)) return 0u;
+        int64_t total = 0;
+        for (int r = 0; r < It; ++r) total += rows[t * 5 + r];
+        const double est = (It - 1) * (Jt - 1) * __builtin_sqrt(static_cast<double>(total > 0 ? total : 0));
+        const double b = est * 0.125;  // 16 inversions at a total of 1,000 reach bucket 63
+        return b >= kBuckets - 1 ? static_cast<uint32_t>(kBuckets - 1) : static_cast<uint32_t>(b);
+    };
+    if (threadIdx.x <= kBuckets) start[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t k = threadIdx.x;
+    const uint32_t key = k < here ? key_of(k) : 0u;
+    if (k < here) atomicAdd(&start[key + 1], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int c = 1; c <= kBuckets; ++c) start[c] += start[c - 1];  // start[c] = tables in buckets below c
+    __syncthreads();
+    if (k < here) order[atomicAdd(&start[key], 1u)] = static_cast<uint16_t>(k);
+    __syncthreads();
+    if (k < here) one_table<G>(base + order[k], streams, I, J, rows, cols, tabs, stats, ck);
 }
 
 // The count is cleared by a kernel, not a memset, so the launch can be
