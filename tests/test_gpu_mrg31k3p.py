@@ -139,6 +139,14 @@ def test_launch_shapes(cfg):
     run(rec, 300 * 11 + 5, P.MRG_NORMAL, P.MRG_F64, cfg=cfg)
 
 
+@pytest.mark.parametrize("S,n", [(65536, 65536 * 300), (100003, 100003 * 130 + 77)])
+def test_default_plan_lockstep_at_scale(S, n):
+    """fp64 uniforms at sizes where the automatic plan runs lockstep blocks
+    (several chunks per stream; an odd stream count with spare waves)."""
+    assert P.mrg_generate_plan(S, n, gen=G)["lockstep"] == 1
+    run(records(workloads.random_seed(S) % np.uint32(P2), S), n, P.MRG_UNIFORM, P.MRG_F64)
+
+
 def test_extreme_states():
     """Words at the top of their ranges and x1 == x2 (z = p1)."""
     st = np.array([[P1 - 1, P1 - 1, P1 - 1, P2 - 1, P2 - 1, P2 - 1],
