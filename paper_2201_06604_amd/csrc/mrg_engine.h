@@ -227,11 +227,16 @@ __device__ __forceinline__ void sincospi_unit(double t, double* sp, double* cp) 
     pc = __builtin_fma(pc, z, 4.0587121264167685);
     pc = __builtin_fma(pc, z, -4.934802200544679);
     const double cs = __builtin_fma(pc, z, 1.0);
-    const int q = static_cast<int>(n) & 3;
-    const double s1 = (q & 1) ? cs : sn;
-    const double c1 = (q & 1) ? sn : cs;
-    *sp = (q & 2) ? -s1 : s1;
-    *cp = (q == 1 || q == 2) ? -c1 : c1;
+    // quadrant q = n mod 4 (n in 0..4): odd q swaps sine and cosine; the sine
+    // is negative for q = 2, 3 (bit 1 of n) and the cosine for q = 1, 2 (bit 1
+    // of n + 1), applied as a flip of the sign bit in the high word
+    const uint32_t ni = static_cast<uint32_t>(static_cast<int>(n));
+    const double s1 = (ni & 1u) ? cs : sn;
+    const double c1 = (ni & 1u) ? sn : cs;
+    const uint32_t sgn_s = (ni << 30) & 0x80000000u;
+    const uint32_t sgn_c = ((ni + 1u) << 30) & 0x80000000u;
+    *sp = __hiloint2double(__double2hiint(s1) ^ static_cast<int>(sgn_s), __double2loint(s1));
+    *cp = __hiloint2double(__double2hiint(c1) ^ static_cast<int>(sgn_c), __double2loint(c1));
 }
 
 
