@@ -483,7 +483,9 @@ class BatchPlan:
 
     def autotune(self, stream=None):
         """Time the candidate shapes and keep the fastest; the workspace is
-        grown first so that every candidate fits (then uploaded again)."""
+        grown first so that every candidate fits (then uploaded again).  A
+        graph captured with the previous workspace must be captured again
+        after this call, and the plan's tables are re-cut for the chosen shape."""
         need = self.autotune_workspace_size()
         if self.workspace is None or self._ws_bytes < need:
             self.alloc_workspace(need)
