@@ -279,10 +279,11 @@ __device__ __forceinline__ double log_unit(double u) {
     static_assert(SCALE == 1 || SCALE == -1 || SCALE == 2 || SCALE == -2, "power-of-two scale");
     int k = __builtin_amdgcn_frexp_exp(u);          // u = mant * 2^k, mant in [1/2, 1)
     double m = __builtin_amdgcn_frexp_mant(u);
-    if (m < 0.70710678118654752440) {
-        m = m + m;
-        k -= 1;
-    }
+    // below sqrt(1/2) the mantissa is doubled (an exponent step, exact) and k
+    // lowered: one integer select and an ldexp rather than a 64-bit select
+    const int lo = m < 0.70710678118654752440 ? 1 : 0;
+    m = __builtin_amdgcn_ldexp(m, lo);
+    k -= lo;
     const double f = m - 1.0;
     const double d = 2.0 + f;
     double y = __builtin_amdgcn_rcp(d);
