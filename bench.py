@@ -5,8 +5,10 @@ seed (2^127 jump-ahead) + generate 2^30 fp64 uniforms from them (4,096 per
 stream, element k*S + s = draw k of stream s) + the state write-back.
 Inputs and outputs stay in HBM.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--copy-probe]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--copy-probe] [--serve-seconds T]
     python bench.py --pmc-summary FETCH_CSV WRITE_CSV BENCH_LOG
+    python bench.py --trace-summary KERNEL_TRACE_CSV BENCH_LOG
+    python bench.py --valu-summary VALU_CSV BENCH_LOG
 """
 import argparse
 import json
@@ -29,6 +31,15 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_2201_06604_amd", "csrc", f)
                for f in ("mrg_kernels.hip", "mrg_engine.h", "mrg_math.h", "mrg_internal.h")]
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "gen_kernel_uniform_f64_262144x4096_traffic.json")
 COPY_PROBE_BYTES = 1 << 30
+# VALU issue ceiling: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one lane-instruction
+# per lane per cycle; gfx950 issues fp64 FMA at full rate)
+VALU_PEAK_LANE_INSTR = 256 * 4 * 16 * 2.4e9
+# Op model: lane-instructions per draw of each kind as the kernels implement
+# the method (counted with SQ_INSTS_VALU on the 2^30-draw launches; frozen
+# here so that a faster kernel shows as a higher fraction, not a smaller model)
+OPS_PER_DRAW = {"f64_uniform": 18.2, "f32_uniform": 19.6, "f64_normal": 54.9, "f64_exponential": 48.3,
+                "f32_normal": 54.9, "f32_exponential": 48.3}
+VALU_JSON = os.path.join(ROOT, "profiles", "gen_kernels_valu_262144x4096.json")
 
 
 def parse():
@@ -45,6 +56,15 @@ def parse():
                     help="skip the MRG31k3p and paper-geometry (rnormGpu example) timings")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="seconds of Poisson arrivals per serving rate and mode")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_LOG"), default=None,
+                    help="per-kernel duration statistics of a rocprofv3 --kernel-trace run of bench.py "
+                         "(markdown on stdout), with the timed launches of the headline kernel "
+                         "separated from its warm-up ones, then exit")
+    ap.add_argument("--valu-summary", nargs=2, metavar=("VALU_CSV", "BENCH_LOG"), default=None,
+                    help="turn a rocprofv3 --pmc SQ_INSTS_VALU run of bench.py into the per-unit "
+                         "instruction counts under profiles/, then exit")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_LOG"), default=None,
                     help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of a "
                          "--copy-probe run into the traffic summary under profiles/, then exit; the "
@@ -118,6 +138,120 @@ def measured_traffic():
     return t["bytes_per_launch"] if t.get("source_sha256") == kernel_sha() else None
 
 
+def trace_summary(kt_csv, bench_log):
+    """Markdown table of per-kernel durations from a rocprofv3 kernel-trace
+    CSV of one bench.py run; the headline kernel (the fp64-uniform generate
+    launch over 2^30 draws) is also summarised over its last `steps`
+    dispatches, the ones inside the timed region, next to the same run's own
+    HIP-event figures from its JSON line."""
+    import csv
+    rows = list(csv.DictReader(open(kt_csv)))
+    line = None
+    with open(bench_log) as f:
+        for ln in f:
+            if ln.startswith("{"):
+                line = json.loads(ln)
+    if line is None:
+        sys.exit("no JSON line in " + bench_log)
+    by = {}
+    for r in rows:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3  # ns -> us
+        by.setdefault(r["Kernel_Name"], []).append((int(r["Start_Timestamp"]), d))
+    total = sum(d for v in by.values() for _, d in v)
+    print("| Kernel | Calls | Avg (us) | Median (us) | Min (us) | Max (us) | % of GPU time |")
+    print("|---|---|---|---|---|---|---|")
+    for k, v in sorted(by.items(), key=lambda kv: -sum(d for _, d in kv[1])):
+        ds = sorted(d for _, d in v)
+        name = k if len(k) <= 90 else k[:87] + "..."
+        print(f"| `{name}` | {len(ds)} | {np.mean(ds):.1f} | {np.median(ds):.1f} | {ds[0]:.1f} | {ds[-1]:.1f} | "
+              f"{100 * sum(ds) / total:.2f} |")
+    gens = [k for k in by if "gen_kernel<0, 0," in k]
+    head = max(gens, key=lambda k: max(d for _, d in by[k]))
+    steps = int(line["steps"])
+    timed = [d for _, d in sorted(by[head])][-steps:]
+    alg = line["roofline"]["alg_bytes_per_launch"]
+    avg = float(np.mean(timed))
+    print()
+    print(f"Headline kernel `{head}`: the last {steps} dispatches (the timed region) average "
+          f"{avg:.1f} us (median {np.median(timed):.1f}, min {min(timed):.1f}); "
+          f"{alg / 1e9:.4f} GB / {avg / 1e3:.4f} ms = {alg / (avg * 1e-6) / 1e9:.1f} GB/s = "
+          f"{alg / (avg * 1e-6) / 1e9 / HBM_PEAK_GBPS:.4f} of {HBM_PEAK_GBPS:.0f} GB/s.")
+    rf = line["roofline"]
+    print(f"The same run's JSON line (HIP events around each timed launch): avg_launch_ms {rf['avg_launch_ms']}, "
+          f"median {rf['launch_ms_median']}, min {rf['launch_ms_min']}, achieved {rf['achieved']} GB/s, "
+          f"frac {rf['frac']}; ms_per_step {line['ms_per_step']}, value {line['value']}.")
+
+
+def valu_summary(valu_csv, bench_log):
+    """Lane-instructions per unit of the measured kernels from a rocprofv3
+    --pmc SQ_INSTS_VALU run of bench.py (wave-instructions per dispatch x 64
+    lanes / the units the dispatch processed), written to the JSON the bench
+    reads while the kernel sources are unchanged.  Units: draws for the
+    2^30-draw generate launches (the dispatch of each kind with the most
+    instructions) and for the last batch launch (a graph replay over the
+    whole mix); tables for the 10^6-table launch."""
+    import csv
+    per = {}
+    for r in csv.DictReader(open(valu_csv)):
+        if r["Counter_Name"] != "SQ_INSTS_VALU":
+            continue
+        key = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    line = None
+    with open(bench_log) as f:
+        for ln in f:
+            if ln.startswith("{"):
+                line = json.loads(ln)
+    if line is None:
+        sys.exit("no JSON line in " + bench_log)
+
+    def biggest(pred):
+        ks = [(v, k) for k, v in per.items() if pred(k[1])]
+        return max(ks)[0] if ks else None
+
+    out = {"source_sha256": line["roofline"]["source_sha256"], "per_unit": {}, "workload": {}}
+    for name, prefix in [("f64_uniform", "gen_kernel<0, 0,"), ("f32_uniform", "gen_kernel<0, 1,"),
+                         ("f64_normal", "gen_kernel<1, 0,"), ("f64_exponential", "gen_kernel<2, 0,")]:
+        v = biggest(lambda k, p=prefix: p in k)
+        if v is not None:
+            out["per_unit"][name] = v * 64 / N
+            out["workload"][name] = f"{S_STREAMS} streams x {PER_STREAM} draws, per draw"
+    v = biggest(lambda k: "tables_kernel" in k)
+    if v is not None:
+        out["per_unit"]["tables_kernel"] = v * 64 / 1_000_000
+        out["workload"]["tables_kernel"] = "10^6 tables of the CFG4 mix, per table"
+    batch = sorted((d, v) for (d, k), v in per.items() if "batch_kernel" in k)
+    if batch and "batched" in line:
+        out["per_unit"]["batch_kernel"] = batch[-1][1] * 64 / line["batched"]["draws"]
+        out["workload"]["batch_kernel"] = "the 4,096-request mix (last launch), per draw"
+    with open(VALU_JSON, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+def valu_profile():
+    """Measured lane-instructions per unit of the kernels the committed VALU
+    counter profile covers, only while the kernel sources are the ones
+    measured (None otherwise)."""
+    if not os.path.exists(VALU_JSON):
+        return None
+    with open(VALU_JSON) as f:
+        t = json.load(f)
+    return t if t.get("source_sha256") == kernel_sha() else None
+
+
+def alu_roofline(ops_per_unit, units, ms, measured_per_unit=None):
+    """VALU roofline entry: ops_per_unit x units lane-instructions in `ms`
+    against the 2.4 GHz issue ceiling."""
+    achieved = ops_per_unit * units / (ms * 1e-3)
+    out = {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(VALU_PEAK_LANE_INSTR / 1e12, 2),
+           "unit": "T lane-instr/s", "frac": round(achieved / VALU_PEAK_LANE_INSTR, 4),
+           "ops_per_unit": ops_per_unit}
+    if measured_per_unit is not None:
+        out["measured_ops_per_unit"] = round(measured_per_unit, 2)
+    return out
+
+
 def timed_median(torch, fn, reps=5, inner=3, warm_ms=50.0):
     """Median over `reps` of the mean time (ms, HIP events on the current
     stream) of `inner` back-to-back calls, after calls for at least `warm_ms`
@@ -172,6 +306,22 @@ def cpu_baseline(seed):
             "cpu_model": model, "nproc": os.cpu_count()}
 
 
+def oracle_threads():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def oracle_rate(gen_seed, S, per, dist, dtype, param=1.0):
+    """The oracle generating `per` draws of each of S streams on the host
+    cores (streams split over threads): (GSamples/s, seconds, threads)."""
+    import oracle as O
+    rec = O.create_streams(O.MRG32K3A, gen_seed.copy(), S)
+    th = oracle_threads()
+    t0 = time.perf_counter()
+    O.generate(O.MRG32K3A, rec, S * per, dist, dtype, param, threads=th)
+    dt = time.perf_counter() - t0
+    return S * per / dt / 1e9, dt, th
+
+
 def bench_small(torch, P, workloads, reps=50):
     """The paper-shaped small case: seed 12345 x 6, 1,024 streams created on
     the device, 1,024 fp64 uniforms each (2^20): launch-bound, so latency per
@@ -209,7 +359,7 @@ def bench_small(torch, P, workloads, reps=50):
             "oracle_one_core_ms": round(oracle_ms, 1)}
 
 
-def bench_batched(torch, P, workloads, reps=3):
+def bench_batched(torch, P, workloads, reps=3, with_oracle=True):
     """4,096 generation requests (lengths log-uniform in [1e3, 1e7], 64-1,024
     streams each, random f32/f64 x uniform/normal/exponential) on consecutive
     streams of one creator: 4,096 back-to-back plain launches against one
@@ -284,14 +434,48 @@ def bench_batched(torch, P, workloads, reps=3):
            "requests": len(reqs), "streams": total_S, "draws": total_n, "output_bytes": out_bytes,
            "plain": stats(lat_p[-1], lat_p), "batched": stats(best_ms, lat_b),
            "batched_tuning": best}
+    kind = {(0, 0): "f64_uniform", (0, 1): "f32_uniform", (1, 0): "f64_normal", (1, 1): "f32_normal",
+            (2, 0): "f64_exponential", (2, 1): "f32_exponential"}
+    ops = sum(r["n"] * OPS_PER_DRAW[kind[(r["dist"], r["dtype"])]] for r in reqs)
+    res["roofline"] = alu_roofline(ops / total_n, total_n, best_ms)
+    res["roofline"]["hbm_frac"] = round(out_bytes / (best_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+    res["roofline"]["kernel"] = "batch_kernel (persistent, graph-replayed)"
     res["speedup_makespan"] = round(res["plain"]["makespan_ms"] / res["batched"]["makespan_ms"], 2)
     res["p99_ratio_plain_over_batched"] = round(res["plain"]["p99_ms"] / res["batched"]["p99_ms"], 2)
     for m in meta:
         del m
+    if with_oracle:
+        res["oracle"] = batch_oracle_sample(reqs, workloads.random_seed())
     return res
 
 
-def bench_tables(torch, P, workloads, reps=10):
+def batch_oracle_sample(reqs, seed, every=16):
+    """The oracle on every 16th request of the batch mix (each on its own
+    streams, reached by one 2^127-step jump per stream offset), requests
+    spread over the host threads."""
+    import oracle as O
+    from concurrent.futures import ThreadPoolExecutor
+    dmap = {0: O.UNIFORM, 1: O.NORMAL, 2: O.EXPONENTIAL}
+    tmap = {0: O.F64, 1: O.F32}
+    sample = reqs[::every]
+
+    def one(r):
+        c = seed.copy()
+        O.jump(O.MRG32K3A, c, r["first_stream"] * 2**127)
+        rec = O.create_streams(O.MRG32K3A, c, r["n_streams"])
+        O.generate(O.MRG32K3A, rec, r["n"], dmap[r["dist"]], tmap[r["dtype"]], 1.0)
+
+    th = oracle_threads()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(th) as ex:
+        list(ex.map(one, sample))
+    dt = time.perf_counter() - t0
+    n = sum(r["n"] for r in sample)
+    return {"value": round(n / dt / 1e9, 4), "unit": "GSamples/s", "cores": th, "kind": "oracle",
+            "sample": f"every {every}th request ({len(sample)} requests, {n} draws, {dt:.2f} s)"}
+
+
+def bench_tables(torch, P, workloads, reps=10, with_oracle=True):
     """Section 4 consumer: 1e6 random 2x2..5x5 tables with fixed margins
     (totals 5..200), one stream each, per launch (HIP events); and fisher.sim
     on the two tables the paper tests (12 x 12 with B = 2^20, 7 x 12 with
@@ -320,7 +504,14 @@ def bench_tables(torch, P, workloads, reps=10):
                        "int32 tables + statistic",
            "ms": round(ms, 3), "Mtables_per_s": round(n / ms / 1e3, 1),
            "GUniforms_per_s": round(draws / ms / 1e6, 2)}
+    vp = valu_profile()
+    if vp and "tables_kernel" in vp.get("per_unit", {}):
+        res["roofline"] = alu_roofline(vp["per_unit"]["tables_kernel"], n, ms)
+        res["roofline"]["kernel"] = "tables_kernel"
+        res["roofline"]["note"] = "ops_per_unit = measured VALU lane-instructions per table (data-dependent loops)"
     del d, tabs, stats
+    if with_oracle:
+        res["oracle"] = tables_oracle_sample(I, J, rows, cols, workloads.random_seed())
     fis = {}
     for name, B, paper_s in (("fisher_month.txt", 1 << 20, 0.348), ("fisher_week.txt", 10027008, 2.030)):
         tab = np.array([[int(v) for v in r] for r in read_golden(name)], dtype=np.int32)
@@ -339,7 +530,47 @@ def bench_tables(torch, P, workloads, reps=10):
             "paper_V100_s": paper_s}
         del d
     res["fisher"] = fis
+    if with_oracle:
+        tab = np.array([[int(v) for v in r] for r in read_golden("fisher_month.txt")], dtype=np.int32)
+        res["fisher"]["oracle"] = fisher_oracle_sample(tab, workloads.random_seed(44))
     return res
+
+
+def tables_oracle_sample(I, J, rows, cols, seed, n=200_000):
+    """The oracle sampling the first 200,000 tables of the mix on the host
+    threads (tables split into contiguous blocks)."""
+    import oracle as O
+    from concurrent.futures import ThreadPoolExecutor
+    rec = O.create_streams(O.MRG32K3A, seed.copy(), n)
+    th = oracle_threads()
+    bounds = np.linspace(0, n, th + 1).astype(int)
+
+    def one(k):
+        a, b = bounds[k], bounds[k + 1]
+        O.tables(O.MRG32K3A, rec[a:b], I[a:b], J[a:b], rows[a:b], cols[a:b])
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(th) as ex:
+        list(ex.map(one, range(th)))
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt / 1e6, 3), "unit": "Mtables/s", "cores": th, "kind": "oracle",
+            "sample": f"first {n} tables of the mix ({dt:.2f} s)"}
+
+
+def fisher_oracle_sample(tab, seed, B=65536):
+    """The oracle's fisher.sim count on the 12 x 12 table with 65,536
+    replicates on the host threads."""
+    import oracle as O
+    from concurrent.futures import ThreadPoolExecutor
+    rec = O.create_streams(O.MRG32K3A, seed.copy(), B)
+    th = oracle_threads()
+    bounds = np.linspace(0, B, th + 1).astype(int)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(th) as ex:
+        list(ex.map(lambda k: O.fisher_count(O.MRG32K3A, rec[bounds[k]:bounds[k + 1]], tab), range(th)))
+    dt = time.perf_counter() - t0
+    return {"value": round(B / dt / 1e6, 3), "unit": "Mtables/s", "cores": th, "kind": "oracle",
+            "sample": f"12x12 table, {B} replicates ({dt:.2f} s)"}
 
 
 def bench_paper(torch, P, workloads, out, reps=5):
@@ -367,7 +598,7 @@ def bench_paper(torch, P, workloads, out, reps=5):
     return res
 
 
-def bench_serving(torch, P, workloads, rates=(2000, 5000, 10000, 20000, 50000), duration=1.0):
+def bench_serving(torch, P, workloads, rates=(2000, 5000, 10000, 20000, 50000), duration=10.0):
     """The request loop: Poisson arrivals from 256 sessions (64 device
     streams each), lengths log-uniform in [1e2, 1e6] fp64 normals, a 32 GB
     output pool; continuous batching on 4 HIP streams against one plain
@@ -380,14 +611,18 @@ def bench_serving(torch, P, workloads, rates=(2000, 5000, 10000, 20000, 50000), 
         for mode, name in ((0, "batched"), (1, "plain")):
             srv = P.Server(256, workloads.random_seed(), pool, mode=mode)
             lat, span = srv.drive((t * 1e9).astype(np.uint64), sess, lens)
-            peak = srv.stats()["pool_peak"]
+            st = srv.stats()
             srv.close()
             lat_ms = lat / 1e6
             row[name] = {"GSamples_per_s": round(float(lens.sum()) / (span / 1e9) / 1e9, 3),
                          "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
                          "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
                          "p999_ms": round(float(np.percentile(lat_ms, 99.9)), 3),
-                         "pool_peak_MB": round(peak / 1e6, 1)}
+                         "pool_peak_MB": round(st["pool_peak"] / 1e6, 1),
+                         "launches": int(st["launches"]), "max_in_flight": int(st["max_in_flight"]),
+                         "max_lanes_busy": int(st["max_lanes_busy"])}
+            print(f"serving {rate}/s {name}: p50 {row[name]['p50_ms']} ms p99 {row[name]['p99_ms']} ms",
+                  file=sys.stderr, flush=True)
         out[f"{rate}_per_s"] = dict(requests=int(len(t)), **row)
     del pool
     return {"workload": f"Poisson arrivals for {duration:g} s, 256 sessions x 64 streams, lengths log-uniform "
@@ -398,6 +633,12 @@ def main():
     args = parse()
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
+        return
+    if args.trace_summary:
+        trace_summary(*args.trace_summary)
+        return
+    if args.valu_summary:
+        valu_summary(*args.valu_summary)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
@@ -486,6 +727,25 @@ def main():
     res["store_only_fill_GBps"] = round(N * 8 / (fill_ms * 1e-3) / 1e9, 1)
     res["achieved_vs_store_only"] = round(achieved / res["store_only_fill_GBps"], 3)
 
+    # store-only ceiling of the generate kernel's own layout (same grid, store
+    # width, row order, barriers, cache policy; no numbers computed), timed
+    # like the headline launches
+    for _ in range(args.warmup):
+        P.mrg_store_ceiling(S_STREAMS, N, P.MRG_F64, out=out)
+    cev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in cev:
+        a.record()
+        P.mrg_store_ceiling(S_STREAMS, N, P.MRG_F64, out=out)
+        b.record()
+    torch.cuda.synchronize()
+    c_ms = [a.elapsed_time(b) for a, b in cev]
+    c_avg = float(np.mean(c_ms))
+    res["store_ceiling"] = {"kernel": "store_ceiling_kernel (the generate kernel's launch shape)",
+                            "avg_launch_ms": round(c_avg, 4), "launch_ms_median": round(float(np.median(c_ms)), 4),
+                            "GBps": round(N * 8 / (c_avg * 1e-3) / 1e9, 1)}
+    res["achieved_vs_store_ceiling"] = round(achieved / res["store_ceiling"]["GBps"], 3)
+    res["roofline"]["frac_of_store_ceiling"] = res["achieved_vs_store_ceiling"]
+
     if not args.no_variants:
         var = {}
         out32 = torch.empty(N, dtype=torch.float32, device=dev)
@@ -493,23 +753,36 @@ def main():
                                        ("f64_normal", P.MRG_NORMAL, P.MRG_F64, out, 8),
                                        ("f64_exponential", P.MRG_EXPONENTIAL, P.MRG_F64, out, 8)]:
             ms = timed_median(torch, lambda: P.mrg_generate(streams, N, dist, dt, 1.0, out=o))
+            gbps = N * esz / (ms * 1e-3) / 1e9
             var[name] = {"GSamples_per_s": round(N / (ms * 1e-3) / 1e9, 2),
-                         "GB_per_s": round(N * esz / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4)}
+                         "GB_per_s": round(gbps, 1), "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
+                         "ms": round(ms, 4)}
+            vp = valu_profile()
+            meas = vp["per_unit"].get(name) if vp else None
+            var[name]["roofline"] = alu_roofline(OPS_PER_DRAW[name], N, ms, meas)
         del out32
+        if not args.no_cpu:
+            import oracle as O
+            for name, od, odt in [("f32_uniform", O.UNIFORM, O.F32), ("f64_normal", O.NORMAL, O.F64),
+                                  ("f64_exponential", O.EXPONENTIAL, O.F64)]:
+                rate, dt_s, th = oracle_rate(seed, 16384, PER_STREAM, od, odt)
+                var[name]["oracle"] = {"value": round(rate, 4), "unit": "GSamples/s", "cores": th,
+                                       "kind": "oracle",
+                                       "sample": f"16384 streams x {PER_STREAM} ({dt_s:.2f} s)"}
         res["variants"] = var
 
     res["small"] = bench_small(torch, P, workloads)
 
     if not args.no_batch:
-        res["batched"] = bench_batched(torch, P, workloads)
+        res["batched"] = bench_batched(torch, P, workloads, with_oracle=not args.no_cpu)
         torch.cuda.empty_cache()
 
     if not args.no_tables:
-        res["tables"] = bench_tables(torch, P, workloads)
+        res["tables"] = bench_tables(torch, P, workloads, with_oracle=not args.no_cpu)
         torch.cuda.empty_cache()
 
     if not args.no_serving:
-        res["serving"] = bench_serving(torch, P, workloads)
+        res["serving"] = bench_serving(torch, P, workloads, duration=args.serve_seconds)
         torch.cuda.empty_cache()
 
     if not args.no_paper:

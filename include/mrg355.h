@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MRG_ABI_VERSION 1
+#define MRG_ABI_VERSION 2
 
 typedef enum {
     MRG_OK = 0,
@@ -45,7 +45,8 @@ typedef enum {
     MRG_E_UNSUPPORTED = -3,   /* generator/dist/dtype combination not built  */
     MRG_E_HIP = -4,           /* a HIP runtime call failed                   */
     MRG_E_NOMEM = -5,         /* host allocation failed / buffer too small   */
-    MRG_E_CORRUPT_STATE = -6  /* import: bad magic, version, length or words */
+    MRG_E_CORRUPT_STATE = -6, /* import: bad magic, version, length or words */
+    MRG_E_BUSY = -7           /* mrg_server_poll: the request is not done yet */
 } mrg_status;
 
 /* Generators.  MRG32k3a: components mod m1 = 2^32-209 and m2 = 2^32-22853,
@@ -144,11 +145,21 @@ mrg_status mrg_streams_create_host(mrg_generator gen, mrg_creator* creator, size
 mrg_status mrg_streams_create_device(mrg_generator gen, mrg_creator* creator, size_t n,
                                      mrg_stream* dev_out, hipStream_t stream);
 
-/* Substream resets on n device stream records (see mrg_reset_kind). */
+/* Substreams (Section 2.1): the period is cut into streams Z steps apart,
+ * and each stream can be cut further into substreams, which the paper notes
+ * clrng does not implement; the record keeps the start of the current
+ * substream as in RngStreams, the package Section 2.1 builds on.  The
+ * substream length is 2^76 steps (MRG32k3a) or 2^72 (MRG31k3p).  This call
+ * applies one of the mrg_reset_kind operations to n device stream records
+ * (4-byte aligned).  n = 0 is a no-op. */
 mrg_status mrg_streams_reset(mrg_generator gen, mrg_stream* dev, size_t n, mrg_reset_kind kind,
                              hipStream_t stream);
 
-/* Advance the current state of n device stream records by `steps` steps. */
+/* Jump-ahead (Section 2.1, which creates streams by advancing the state Z
+ * steps with a matrix power): the current state of each of n device stream
+ * records advances by `steps` steps (any count below 2^64), as if that many
+ * numbers had been drawn; initial and substream states stay.  n = 0 or
+ * steps = 0 is a no-op. */
 mrg_status mrg_streams_advance(mrg_generator gen, mrg_stream* dev, size_t n, uint64_t steps,
                                hipStream_t stream);
 
@@ -267,6 +278,44 @@ mrg_status mrg_fisher_sim(mrg_generator gen, mrg_stream* dev_streams, uint64_t B
 double     mrg_fisher_pvalue(uint64_t count, uint64_t B);
 
 /* ------------------------------------------------------------------------
+ * Diagnostics.  Neither call reads or changes any stream.
+ * ------------------------------------------------------------------------ */
+
+/* Functions mrg_transform_accuracy checks.  The normal (Algorithm 1 of
+ * Section 3.1) and exponential (Section 3.2) transforms evaluate them with the
+ * library's own code, which leaves out the range reduction and special cases
+ * of the general functions (a uniform lies in [2^-33, 1) and is never zero,
+ * subnormal or non-finite). */
+typedef enum {
+    MRG_CHECK_LOG = 0,    /* log(u), u = z/(m1+1): exponential draws, Box-Muller radius */
+    MRG_CHECK_SQRT = 1,   /* sqrt(x), x = -2 log(u): the Box-Muller radius R          */
+    MRG_CHECK_SINPI = 2,  /* sin(pi t), t = 2u: the Box-Muller angle                   */
+    MRG_CHECK_COSPI = 3   /* cos(pi t), t = 2u                                         */
+} mrg_check_fn;
+
+/* For every integer z in [z_begin, z_end), the generator output a step can
+ * produce (1 <= z_begin <= z_end <= m1 + 1), evaluate function `fn` at the
+ * input that z gives the transforms, once with the library's code and once
+ * with the HIP device math library (log, sqrt, sincospi; MRG_CHECK_SQRT feeds
+ * both the library's -2 log(u)), and count how many doubles apart the two
+ * results are.  dev_result (device, 8 uint64, 8-byte aligned) receives:
+ * [0]..[3] the number of inputs 0, 1, 2, 3 apart, [4] 4 or more apart,
+ * [5] (largest distance << 32) | the largest z at that distance (distance
+ * capped at 2^32 - 1), [6] and [7] zero.  The call clears dev_result itself
+ * with a kernel (no memset).  Asynchronous on `stream`. */
+mrg_status mrg_transform_accuracy(mrg_generator gen, mrg_check_fn fn, uint64_t z_begin, uint64_t z_end,
+                                  uint64_t* dev_result, hipStream_t stream);
+
+/* Store-only ceiling of mrg_generate: writes 0.5 into the n elements of
+ * dev_out (MRG_F64 or MRG_F32, aligned to its element size) with exactly the
+ * store pattern of mrg_generate for MRG_UNIFORM draws of that dtype from
+ * n_streams streams -- the same grid, per-lane store width, row order,
+ * per-row barriers and cache policy -- and computes nothing else.  Its time
+ * is what that write layout allows by itself.  n must be a multiple of
+ * n_streams (whole rows).  Asynchronous on `stream`. */
+mrg_status mrg_store_ceiling(size_t n_streams, uint64_t n, mrg_dtype dtype, void* dev_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Batching: many generation requests of uneven lengths, each on its own
  * streams, in one persistent launch (graph-capturable).  Every request gives
  * exactly the numbers and final states that mrg_generate would give for it.
@@ -371,9 +420,12 @@ mrg_status mrg_batch_autotune_workspace_size(const mrg_batch_plan* plan, size_t*
  *     host-visible memory when its output is stored.
  *   - mode 1 replaces batching by one plain launch per request at admission,
  *     in submission order on one HIP stream (the comparison baseline).
- * mrg_server_create allocates the session streams, the per-lane workspaces
- * (device) and the completion flags and staging buffers (pinned host
- * memory), and starts one scheduler thread; nothing is allocated afterwards.
+ * Memory: the caller owns the device memory -- the output pool and a
+ * workspace (mrg_server_workspace_size bytes, 256-byte aligned) that holds
+ * the session stream records and one batch workspace per lane.  The library
+ * allocates, in mrg_server_create and nowhere else, only pinned host memory
+ * for the per-lane completion flags (host-visible, written by the kernels)
+ * and table staging, plus HIP streams and events.
  * ------------------------------------------------------------------------ */
 
 typedef struct {
@@ -386,6 +438,9 @@ typedef struct {
     uint32_t max_batch;            /* requests per launch at most (0 = 256) */
     uint32_t mode;                 /* 0 = continuous batching, 1 = one plain launch per request */
     uint32_t tile_units;           /* 0 = 2048 */
+    void* workspace;               /* device memory for session streams and lane workspaces
+                                      (caller-owned, 256-byte aligned, not overlapping the pool) */
+    size_t workspace_bytes;        /* at least mrg_server_workspace_size(cfg) */
 } mrg_server_cfg;
 
 typedef struct {
@@ -394,11 +449,21 @@ typedef struct {
     uint64_t launches;             /* batches (mode 0) or plain launches (mode 1) */
     uint64_t pool_in_use, pool_peak;
     uint64_t max_in_flight;        /* most requests on the device at once */
+    uint64_t max_lanes_busy;       /* most lanes with a launch in flight at once (mode 0) */
 } mrg_server_stats;
 
 typedef struct mrg_server mrg_server;  /* opaque */
 
 uint64_t   mrg_now_ns(void);           /* the steady clock the server uses */
+
+/* Bytes of device workspace a server with this configuration needs (the
+ * workspace fields of cfg are not read).  Host only. */
+mrg_status mrg_server_workspace_size(const mrg_server_cfg* cfg, size_t* bytes);
+
+/* Creates the session streams (in the workspace) and starts the scheduler
+ * thread.  MRG_E_NOMEM when the workspace is smaller than
+ * mrg_server_workspace_size; MRG_E_INVALID_ARG when the pool or workspace is
+ * missing, misaligned or the two overlap. */
 mrg_status mrg_server_create(const mrg_server_cfg* cfg, mrg_server** srv);
 void       mrg_server_destroy(mrg_server* srv);  /* waits for work in flight */
 
@@ -411,15 +476,18 @@ mrg_status mrg_server_submit(mrg_server* srv, uint32_t session, uint64_t n, mrg_
                              mrg_dtype dtype, double param, uint64_t t_arrival_ns, uint64_t* ticket,
                              uint64_t* offset_out);
 
-/* Non-blocking query: *done = 1 once the output is in the pool; then
- * *dev_out points at it (n elements) and *t_done_ns is when the server saw
- * it complete. */
+/* Non-blocking query.  MRG_OK with *done = 1 once the output is in the
+ * pool; then *dev_out points at it (n elements) and *t_done_ns is when the
+ * server saw it complete.  MRG_E_BUSY with *done = 0 while the request is
+ * queued or running (not an error: poll again). */
 mrg_status mrg_server_poll(mrg_server* srv, uint64_t ticket, int* done, void** dev_out,
                            uint64_t* t_done_ns);
 
 /* Give the output memory of a completed request back to the pool. */
 mrg_status mrg_server_release(mrg_server* srv, uint64_t ticket);
 
+/* Counters of the server so far (host struct).  The struct type already
+ * carries the name mrg_server_stats, hence the _get. */
 mrg_status mrg_server_stats_get(mrg_server* srv, mrg_server_stats* out);
 
 /* Open-loop replay on the calling thread: request i (session[i], n_draws[i]

@@ -21,8 +21,10 @@ MRG_UNIFORM, MRG_NORMAL, MRG_EXPONENTIAL, MRG_RAW = 0, 1, 2, 3
 MRG_F64, MRG_F32, MRG_U32 = 0, 1, 2
 MRG_RESET_STREAM, MRG_RESET_SUBSTREAM, MRG_NEXT_SUBSTREAM = 0, 1, 2
 MRG_OK = 0
+MRG_E_BUSY = -7
 STATUS = {0: "MRG_OK", -1: "MRG_E_INVALID_ARG", -2: "MRG_E_INVALID_SEED", -3: "MRG_E_UNSUPPORTED",
-          -4: "MRG_E_HIP", -5: "MRG_E_NOMEM", -6: "MRG_E_CORRUPT_STATE"}
+          -4: "MRG_E_HIP", -5: "MRG_E_NOMEM", -6: "MRG_E_CORRUPT_STATE", -7: "MRG_E_BUSY"}
+MRG_CHECK_LOG, MRG_CHECK_SQRT, MRG_CHECK_SINPI, MRG_CHECK_COSPI = 0, 1, 2, 3
 REC_WORDS = 18
 
 
@@ -69,13 +71,14 @@ class mrg_server_cfg(ctypes.Structure):
     _fields_ = [("n_sessions", ctypes.c_uint32), ("streams_per_session", ctypes.c_uint32),
                 ("seed", ctypes.c_uint32 * 6), ("pool", ctypes.c_void_p), ("pool_bytes", ctypes.c_size_t),
                 ("lanes", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("mode", ctypes.c_uint32),
-                ("tile_units", ctypes.c_uint32)]
+                ("tile_units", ctypes.c_uint32), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
 
 
 class mrg_server_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "released", "rejected",
                                                 "samples_completed", "launches", "pool_in_use",
-                                                "pool_peak", "max_in_flight")]
+                                                "pool_peak", "max_in_flight", "max_lanes_busy")]
 
 
 _lib = None
@@ -128,7 +131,10 @@ def lib():
             "mrg_fisher_sim": (i32, [i32, vp, u64, i32, i32, ctypes.POINTER(ctypes.c_int32), vp, vp,
                                      ctypes.POINTER(ctypes.c_double), vp]),
             "mrg_fisher_pvalue": (ctypes.c_double, [u64, u64]),
+            "mrg_transform_accuracy": (i32, [i32, i32, u64, u64, vp, vp]),
+            "mrg_store_ceiling": (i32, [sz, u64, i32, vp, vp]),
             "mrg_now_ns": (u64, []),
+            "mrg_server_workspace_size": (i32, [ctypes.POINTER(mrg_server_cfg), ctypes.POINTER(sz)]),
             "mrg_server_create": (i32, [ctypes.POINTER(mrg_server_cfg), ctypes.POINTER(vp)]),
             "mrg_server_destroy": (None, [vp]),
             "mrg_server_submit": (i32, [vp, ctypes.c_uint32, u64, i32, i32, ctypes.c_double, u64,
@@ -156,7 +162,8 @@ EXPORTED = ["mrg_abi_version", "mrg_status_string", "mrg_last_error", "mrg_seed_
             "mrg_batch_plan_create", "mrg_batch_plan_destroy", "mrg_batch_workspace_size",
             "mrg_batch_tile_count", "mrg_batch_upload", "mrg_batch_launch",
             "mrg_batch_request_times", "mrg_batch_autotune", "mrg_batch_autotune_workspace_size",
-            "mrg_now_ns", "mrg_server_create",
+            "mrg_transform_accuracy", "mrg_store_ceiling",
+            "mrg_now_ns", "mrg_server_workspace_size", "mrg_server_create",
             "mrg_server_destroy", "mrg_server_submit", "mrg_server_poll", "mrg_server_release",
             "mrg_server_stats_get", "mrg_server_drive"]
 
@@ -410,6 +417,35 @@ def mrg_fisher_pvalue(count, B):
     return lib().mrg_fisher_pvalue(int(count), int(B))
 
 
+def mrg_transform_accuracy(fn, z_begin=1, z_end=None, gen=MRG_GEN_MRG32K3A, result=None, stream=None):
+    """Distance in ulp between the library's own log / sqrt / sin(pi t) /
+    cos(pi t) and the HIP device math library over every generator output z
+    in [z_begin, z_end) (default: all of [1, m1]).  Returns a dict with the
+    histogram (0, 1, 2, 3, >= 4 ulp), the largest distance and the z where it
+    occurs.  Synchronises the stream."""
+    import torch
+    if z_end is None:
+        z_end = (4294967087 if gen == MRG_GEN_MRG32K3A else 2147483647) + 1
+    if result is None:
+        result = torch.empty(8, dtype=torch.int64, device="cuda")
+    _need(result, 64, "result", 8)
+    _check(lib().mrg_transform_accuracy(gen, fn, z_begin, z_end, _dptr(result), _stream(stream)))
+    r = result.cpu().numpy().view(np.uint64)
+    return {"hist": [int(v) for v in r[:5]], "max_ulp": int(r[5] >> np.uint64(32)),
+            "z_at_max": int(r[5] & np.uint64(0xffffffff))}
+
+
+def mrg_store_ceiling(n_streams, n, dtype=MRG_F64, out=None, stream=None):
+    """Write 0.5 into n elements of `out` with mrg_generate's store pattern
+    for uniforms of this dtype over n_streams streams (nothing computed)."""
+    esz = 8 if dtype == MRG_F64 else 4
+    if out is None:
+        out = new_output(n, dtype)
+    _need(out, n * esz, "output", esz)
+    _check(lib().mrg_store_ceiling(n_streams, n, dtype, _dptr(out), _stream(stream)))
+    return out
+
+
 def as_u32(t):
     """Device int32 tensor -> host numpy uint32 (bit reinterpretation)."""
     return t.detach().cpu().numpy().view(np.uint32)
@@ -516,6 +552,12 @@ class Server:
         cfg.pool = pool.data_ptr()
         cfg.pool_bytes = pool.numel() * pool.element_size()
         cfg.lanes, cfg.max_batch, cfg.mode, cfg.tile_units = lanes, max_batch, mode, tile_units
+        need = ctypes.c_size_t()
+        _check(lib().mrg_server_workspace_size(ctypes.byref(cfg), ctypes.byref(need)))
+        import torch
+        self.workspace = torch.empty(need.value + 256, dtype=torch.uint8, device=pool.device)
+        cfg.workspace = self.workspace.data_ptr() + (-self.workspace.data_ptr()) % 256
+        cfg.workspace_bytes = need.value
         self._s = ctypes.c_void_p()
         _check(lib().mrg_server_create(ctypes.byref(cfg), ctypes.byref(self._s)))
         self.S = streams_per_session or 64
@@ -524,6 +566,7 @@ class Server:
         if getattr(self, "_s", None) and self._s.value:
             lib().mrg_server_destroy(self._s)
             self._s = None
+        self.workspace = None
 
     def __del__(self):
         if _lib is not None:
@@ -547,7 +590,10 @@ class Server:
         d = ctypes.c_int()
         p = ctypes.c_void_p()
         t = ctypes.c_uint64()
-        _check(lib().mrg_server_poll(self._s, ticket, ctypes.byref(d), ctypes.byref(p), ctypes.byref(t)))
+        st = lib().mrg_server_poll(self._s, ticket, ctypes.byref(d), ctypes.byref(p), ctypes.byref(t))
+        if st == MRG_E_BUSY:
+            return False, None, 0
+        _check(st)
         return bool(d.value), p.value, t.value
 
     def release(self, ticket):

@@ -5,12 +5,14 @@
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmrg355.so")
-SOURCES = ["mrg_kernels.hip", "mrg_tables.hip", "mrg_api.cpp", "mrg_batch.cpp", "mrg_server.cpp"]
+SOURCES = ["mrg_kernels.hip", "mrg_tables.hip", "mrg_selfcheck.hip", "mrg_api.cpp", "mrg_batch.cpp",
+           "mrg_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -29,17 +31,22 @@ def _compile(src, obj, extra=()):
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source (in parallel) and link libmrg355.so."""
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    jobs = []
     for s in SOURCES:
         src = os.path.join(CSRC, s)
         obj = os.path.join(objdir, s + ".o")
         extra = [] if s.endswith(".hip") else ["-x", "hip"]
         if verbose:
             print("hipcc", s, flush=True)
-        _compile(src, obj, extra)
-        objs.append(obj)
+        jobs.append((src, obj, extra))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "0")) or os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        for f in [ex.submit(_compile, *j) for j in jobs]:
+            f.result()
+    objs = [j[1] for j in jobs]
     tmp = LIB + ".tmp"
     subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs,
                    check=True, cwd=CSRC)
@@ -47,15 +54,5 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
-def disassemble(out_path: str) -> None:
-    """Write the gfx950 assembly of the kernels (for inspection)."""
-    cmd = [HIPCC] + HIP_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC,
-                                 "--cuda-device-only", "-S", os.path.join(CSRC, "mrg_kernels.hip"),
-                                 "-o", out_path]
-    subprocess.run(cmd, check=True, cwd=CSRC)
-
-
 if __name__ == "__main__":
     build(verbose=True)
-    if len(sys.argv) > 1 and sys.argv[1] == "--asm":
-        disassemble(sys.argv[2])

@@ -83,6 +83,7 @@ const char* mrg_status_string(mrg_status st) {
         case MRG_E_HIP: return "HIP runtime error";
         case MRG_E_NOMEM: return "out of memory / buffer too small";
         case MRG_E_CORRUPT_STATE: return "corrupt saved state";
+        case MRG_E_BUSY: return "not done yet";
     }
     return "unknown status";
 }
@@ -344,19 +345,25 @@ mrg_status mrg_fisher_sim(mrg_generator gen, mrg_stream* dev_streams, uint64_t B
     if (reinterpret_cast<uintptr_t>(dev_count) % 8 || reinterpret_cast<uintptr_t>(dev_stats) % 8 ||
         reinterpret_cast<uintptr_t>(dev_streams) % 4)
         return fail(MRG_E_INVALID_ARG, "misaligned pointer");
-    int32_t r[kFisherMaxDim] = {0}, c[kFisherMaxDim] = {0};
+    // margins summed in 64 bits and narrowed only after the total is known
+    // to be at most 2^20 (entries up to 2^31 - 1 cannot overflow them)
+    int64_t r64[kFisherMaxDim] = {0}, c64[kFisherMaxDim] = {0};
     int64_t total = 0;
-    double stat = 0.0;  // -sum log(n!), row-major, from the same values as the device table
     for (int i = 0; i < I; ++i)
         for (int j = 0; j < J; ++j) {
             const int32_t v = observed[i * J + j];
             if (v < 0) return fail(MRG_E_INVALID_ARG, "negative entry in the observed table");
-            r[i] += v;
-            c[j] += v;
+            r64[i] += v;
+            c64[j] += v;
             total += v;
-            stat -= host_log_factorial(v);
         }
     if (total > kTableMaxTotal) return fail(MRG_E_INVALID_ARG, "grand total above 2^20");
+    int32_t r[kFisherMaxDim] = {0}, c[kFisherMaxDim] = {0};
+    for (int i = 0; i < I; ++i) r[i] = static_cast<int32_t>(r64[i]);
+    for (int j = 0; j < J; ++j) c[j] = static_cast<int32_t>(c64[j]);
+    double stat = 0.0;  // -sum log(n!), row-major, from the same values as the device table
+    for (int i = 0; i < I; ++i)
+        for (int j = 0; j < J; ++j) stat -= host_log_factorial(observed[i * J + j]);
     const double threshold = stat / (1.0 + 64.0 * DBL_EPSILON);
     hipError_t e = launch_fisher(gid(gen), reinterpret_cast<uint32_t*>(dev_streams), B, I, J, r, c, threshold,
                                  reinterpret_cast<unsigned long long*>(dev_count), dev_stats, stream);
@@ -367,6 +374,41 @@ mrg_status mrg_fisher_sim(mrg_generator gen, mrg_stream* dev_streams, uint64_t B
 
 double mrg_fisher_pvalue(uint64_t count, uint64_t B) {
     return (1.0 + static_cast<double>(count)) / (static_cast<double>(B) + 1.0);
+}
+
+mrg_status mrg_transform_accuracy(mrg_generator gen, mrg_check_fn fn, uint64_t z_begin, uint64_t z_end,
+                                  uint64_t* dev_result, hipStream_t stream) {
+    if (mrg_status st = check_gen(gen)) return st;
+    if (fn != MRG_CHECK_LOG && fn != MRG_CHECK_SQRT && fn != MRG_CHECK_SINPI && fn != MRG_CHECK_COSPI)
+        return fail(MRG_E_INVALID_ARG, "unknown function %d", static_cast<int>(fn));
+    const uint64_t m1 = gen == MRG_GEN_MRG32K3A ? kM1 : kP1;
+    if (z_begin < 1 || z_begin > z_end || z_end > m1 + 1)
+        return fail(MRG_E_INVALID_ARG, "z range must satisfy 1 <= z_begin <= z_end <= m1 + 1");
+    if (!dev_result || reinterpret_cast<uintptr_t>(dev_result) % 8)
+        return fail(MRG_E_INVALID_ARG, "dev_result is NULL or misaligned");
+    hipError_t e = launch_accuracy(gid(gen), static_cast<int>(fn), z_begin, z_end,
+                                   reinterpret_cast<unsigned long long*>(dev_result), stream);
+    if (e != hipSuccess) return hip_fail(e, "accuracy launch");
+    return ok();
+}
+
+mrg_status mrg_store_ceiling(size_t n_streams, uint64_t n, mrg_dtype dtype, void* dev_out, hipStream_t stream) {
+    if (dtype != MRG_F64 && dtype != MRG_F32) return fail(MRG_E_INVALID_ARG, "dtype must be MRG_F64 or MRG_F32");
+    GenLaunch L;
+    bool noop;
+    if (mrg_status st = generate_shape(MRG_GEN_MRG32K3A, n_streams, n, MRG_UNIFORM, dtype, 1.0, nullptr, L, &noop))
+        return st;
+    if (noop) return ok();
+    if (n % n_streams) return fail(MRG_E_INVALID_ARG, "n must be a multiple of n_streams");
+    if (!dev_out) return fail(MRG_E_INVALID_ARG, "dev_out is NULL");
+    const size_t esz = dtype == MRG_F64 ? 8 : 4;
+    if (reinterpret_cast<uintptr_t>(dev_out) % esz)
+        return fail(MRG_E_INVALID_ARG, "output not aligned to its element size");
+    L.out = dev_out;
+    plan_generate(L);
+    hipError_t e = launch_store_ceiling(L, stream);
+    if (e != hipSuccess) return hip_fail(e, "store ceiling launch");
+    return ok();
 }
 
 mrg_status mrg_streams_export_size(size_t n, int with_creator, size_t* bytes) {

@@ -38,6 +38,7 @@ struct mrg_batch_plan {
     std::vector<uint64_t> fin_pre;
     uint64_t fin_total;
     size_t off_slots, off_reqs, off_tiles, off_fin_req, off_fin_pre, bytes;
+    std::vector<char> packed;  // the static tables as uploaded (workspace bytes from off_reqs on)
 };
 
 namespace {
@@ -98,6 +99,20 @@ bool disjoint(std::vector<std::pair<uintptr_t, uintptr_t>> v) {
     for (size_t i = 1; i < v.size(); ++i)
         if (v[i].first < v[i - 1].second) return false;
     return true;
+}
+
+// Static tables of a plan, laid out as in the workspace from off_reqs on,
+// into P.packed.
+void pack_tables(mrg_batch_plan& P) {
+    P.packed.assign(P.bytes - P.off_reqs, 0);
+    char* host = P.packed.data();
+    auto put = [&](size_t off, const void* src, size_t n) {
+        if (n) std::memcpy(host + (off - P.off_reqs), src, n);
+    };
+    put(P.off_reqs, P.reqs.data(), P.reqs.size() * sizeof(BatchReq));
+    put(P.off_tiles, P.tiles.data(), P.tiles.size() * sizeof(BatchTile));
+    put(P.off_fin_req, P.fin_req.data(), P.fin_req.size() * sizeof(uint32_t));
+    put(P.off_fin_pre, P.fin_pre.data(), P.fin_pre.size() * sizeof(uint64_t));
 }
 
 // (Re)cut the plan's requests into tiles for its tile_units / wide setting.
@@ -192,6 +207,7 @@ mrg_status build(mrg_batch_plan& P) {
     P.off_fin_req = align_up(P.off_tiles + P.tiles.size() * sizeof(BatchTile), 256);
     P.off_fin_pre = align_up(P.off_fin_req + P.fin_req.size() * sizeof(uint32_t), 256);
     P.bytes = align_up(P.off_fin_pre + P.fin_pre.size() * sizeof(uint64_t), 256);
+    pack_tables(P);
     return MRG_OK;
 }
 
@@ -212,22 +228,8 @@ BatchLaunch launch_args(const mrg_batch_plan& P, void* ws) {
     return B;
 }
 
-// Static tables of a plan, laid out as in the workspace from off_reqs on.
-void pack_tables(const mrg_batch_plan& P, char* host) {
-    std::memset(host, 0, P.bytes - P.off_reqs);
-    auto put = [&](size_t off, const void* src, size_t n) {
-        if (n) std::memcpy(host + (off - P.off_reqs), src, n);
-    };
-    put(P.off_reqs, P.reqs.data(), P.reqs.size() * sizeof(BatchReq));
-    put(P.off_tiles, P.tiles.data(), P.tiles.size() * sizeof(BatchTile));
-    put(P.off_fin_req, P.fin_req.data(), P.fin_req.size() * sizeof(uint32_t));
-    put(P.off_fin_pre, P.fin_pre.data(), P.fin_pre.size() * sizeof(uint64_t));
-}
-
 mrg_status upload(const mrg_batch_plan& P, void* ws, hipStream_t stream) {
-    std::vector<char> host(P.bytes - P.off_reqs);
-    pack_tables(P, host.data());
-    hipError_t e = hipMemcpyAsync(static_cast<char*>(ws) + P.off_reqs, host.data(), host.size(),
+    hipError_t e = hipMemcpyAsync(static_cast<char*>(ws) + P.off_reqs, P.packed.data(), P.packed.size(),
                                   hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return mrg355_fail(MRG_E_HIP, "batch upload: %s", hipGetErrorString(e));
@@ -288,7 +290,9 @@ mrg_status plan_internal(const std::vector<PlanReq>& reqs, uint32_t tile_units, 
 
 size_t plan_bytes(const mrg_batch_plan* P) { return P->bytes; }
 size_t plan_table_offset(const mrg_batch_plan* P) { return P->off_reqs; }
-void plan_pack_tables(const mrg_batch_plan* P, char* host) { pack_tables(*P, host); }
+void plan_pack_tables(const mrg_batch_plan* P, char* host) {
+    if (!P->packed.empty()) std::memcpy(host, P->packed.data(), P->packed.size());
+}
 
 mrg_status plan_launch(const mrg_batch_plan* P, void* ws, BatchSlot* host_slots, hipStream_t stream) {
     return launch(*P, ws, stream, host_slots);

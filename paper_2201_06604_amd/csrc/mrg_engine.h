@@ -202,8 +202,8 @@ struct F64Engine {
 // factor of two, or n = 0); sin(pi r) and cos(pi r) by their Taylor series in
 // r^2 with pi folded into the coefficients (sine through r^17, cosine through
 // r^16: the next terms are below 2^-58 at |r| = 1/4); the quadrant n mod 4
-// swaps and negates.  Accuracy is checked against the library sincospi over
-// every uniform the generators can produce.
+// swaps and negates.  mrg_transform_accuracy compares both results with the
+// HIP library's sincospi over any range of generator outputs.
 __device__ __forceinline__ void sincospi_unit(double t, double* sp, double* cp) {
     const double n = __builtin_rint(t + t);
     const double r = __builtin_fma(n, -0.5, t);
@@ -245,8 +245,9 @@ __device__ __forceinline__ void sincospi_unit(double t, double* sp, double* cp) 
 // cases of a general square root are left out.  Goldschmidt's iteration from
 // the hardware reciprocal square root y ~ 1/sqrt(x): g ~ sqrt(x) and
 // h ~ 1/(2 sqrt(x)) are refined together once, then two Newton corrections
-// g += h (x - g^2) with exact residuals (FMA).  Checked against the library
-// sqrt, bit for bit, over every radius argument either generator can produce.
+// g += h (x - g^2) with exact residuals (FMA).  mrg_transform_accuracy
+// compares it with the HIP library's sqrt on the radius argument of any range
+// of generator outputs.
 __device__ __forceinline__ double sqrt_radius(double x) {
     const double y = __builtin_amdgcn_rsq(x);
     double g = x * y;
@@ -262,15 +263,16 @@ __device__ __forceinline__ double sqrt_radius(double x) {
 
 // log(u) for the generators' uniforms, u in [2^-33, 1): never zero,
 // subnormal, negative or non-finite, so no special cases.  u = m 2^k with m
-// in [sqrt(1/2), sqrt(2)); f = m - 1 (exact); s = f / (2 + f); log(m) =
-// 2 atanh(s) = 2s + 2s (s^2/3 + s^4/5 + ... + s^18/19) (|s| <= 0.1716, so the
-// next term is below 2^-55 relative); log(u) = k ln2 + log(m) with ln2 split
-// so that k * ln2_hi is exact.  The quotient uses the hardware reciprocal
-// (relative error below 5e-8 on these divisors, measured over every input),
-// one Newton step (error ~2e-15) and one residual correction q += (f - q d) y,
-// which leaves an error of order 1e-29 before rounding; a second Newton step
-// changed no result over all inputs of either generator.  Accuracy is checked
-// against the library log over every uniform the generators can produce.
+// in [sqrt(1/2), sqrt(2)); f = m - 1 (exact); s = f / d with d = 2 + f;
+// log(m) = 2 atanh(s) = 2s + 2s (s^2/3 + s^4/5 + ... + s^18/19) (|s| <=
+// 0.1716, so the next term is below 2^-55 relative); log(u) = k ln2 + log(m)
+// with ln2 split so that k * ln2_hi is exact.  d = 2 + f is rounded (f can
+// carry a bit below d's last place), so s has up to about one ulp of relative
+// error whatever the division does; the quotient itself uses the hardware
+// reciprocal (relative error below 5e-8 on these divisors), one Newton step
+// and one residual correction q += (f - q d) y, which leave a quotient of the
+// rounded d accurate far below an ulp.  mrg_transform_accuracy compares the
+// result with the HIP library's log over any range of generator outputs.
 // SCALE (1, -1, 2 or -2) multiplies the result: it is folded into the last
 // three steps' constants, and scaling by a power of two commutes with
 // rounding, so log_unit<SCALE>(u) is bit for bit SCALE * log_unit(u).

@@ -144,6 +144,12 @@ struct PaperLaunch {
 void plan_paper(PaperLaunch& L);
 hipError_t launch_paper(const PaperLaunch& L, int gen, hipStream_t s);
 
+// Diagnostics (mrg_selfcheck.hip, mrg_kernels.hip).
+constexpr int kAccuracyBins = 5;   // distances 0, 1, 2, 3 and >= 4 ulp
+constexpr int kAccuracyWords = 8;  // bins, the packed worst case, two reserved words
+hipError_t launch_accuracy(int gen, int fn, uint64_t z0, uint64_t z1, unsigned long long* res, hipStream_t s);
+hipError_t launch_store_ceiling(const GenLaunch& L, hipStream_t s);
+
 // Host-side jump math (same tables the device uses).
 void host_jump_pow2(int gen, uint32_t state[6], uint64_t k, bool stream_tables);  // A^(k [* Z]) state
 

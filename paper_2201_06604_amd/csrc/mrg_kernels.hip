@@ -23,6 +23,7 @@
 // Both produce identical integers; tests check both against the oracle.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "mrg_engine.h"
@@ -898,6 +899,74 @@ static hipError_t launch_gen_only(const GenLaunch& L, hipStream_t s) {
         default:
             return launch_dd<kRaw, kU32>(L, s);
     }
+}
+
+// ------------------------------------------------------ store-only ceiling
+// The store pattern of gen_kernel for uniforms (same block -> (stream block,
+// chunk) map, XCD remap, per-lane store width, row order, per-row barriers
+// and cache policy) with a constant in place of the numbers: its time is
+// what the layout allows the writes alone.  Full rows only (n a multiple of
+// S, checked by the caller).
+template <typename T, int SPL, bool NT, bool LOCK>
+__global__ void __launch_bounds__(1024) store_ceiling_kernel(GenLaunch L, T value) {
+    uint32_t bx = blockIdx.x, by = blockIdx.y;
+    if (L.xcd) {
+        const uint32_t total = gridDim.x * gridDim.y;
+        uint32_t lin = blockIdx.x + blockIdx.y * gridDim.x;
+        lin = (lin % 8) * (total / 8) + lin / 8;
+        bx = lin % gridDim.x;
+        by = lin / gridDim.x;
+    }
+    constexpr uint32_t ESZ = sizeof(T);
+    constexpr uint32_t WS = 64 * SPL;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t sblk = bx * (blockDim.x >> 6) + wave;
+    const bool live = sblk < (L.S + WS - 1) / WS;
+    if (!LOCK && !live) return;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t first = sblk * WS;
+    const bool mine = live && first + lane * SPL < L.S;
+    const uint64_t u0 = static_cast<uint64_t>(by) * L.chunk;
+    const uint64_t u1 = min(u0 + L.chunk, L.q);
+    const uint64_t rowstep = static_cast<uint64_t>(L.S) * ESZ;
+    const uint64_t rest = live ? static_cast<uint64_t>(L.S - first) * ESZ : 0;
+    const uint32_t nrec = rest > 0xffffffffull ? 0xffffffffu : static_cast<uint32_t>(rest);
+    const uint32_t voff = lane * SPL * ESZ;
+    const char* row = static_cast<const char*>(L.out) + (u0 * L.S + (live ? first : 0)) * ESZ;
+    Pack<T, SPL> p;
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) p.v[i] = value;
+    for (uint64_t k = u0; k < u1; ++k) {
+        if (mine) store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, p);
+        row += rowstep;
+        if constexpr (LOCK) __builtin_amdgcn_s_barrier();
+    }
+}
+
+template <typename T, int SPL>
+static hipError_t launch_ceiling_t(const GenLaunch& L, T value, hipStream_t s) {
+    const unsigned wpb = static_cast<unsigned>(L.block) / 64;
+    const uint64_t n_sblk = (static_cast<uint64_t>(L.S) + 64 * SPL - 1) / (64 * SPL);
+    dim3 grid(static_cast<unsigned>((n_sblk + wpb - 1) / wpb), L.n_chunks);
+    if (L.nontemporal) {
+        if (L.lock) hipLaunchKernelGGL((store_ceiling_kernel<T, SPL, true, true>), grid, dim3(L.block), 0, s, L, value);
+        else hipLaunchKernelGGL((store_ceiling_kernel<T, SPL, true, false>), grid, dim3(L.block), 0, s, L, value);
+    } else {
+        if (L.lock) hipLaunchKernelGGL((store_ceiling_kernel<T, SPL, false, true>), grid, dim3(L.block), 0, s, L, value);
+        else hipLaunchKernelGGL((store_ceiling_kernel<T, SPL, false, false>), grid, dim3(L.block), 0, s, L, value);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_store_ceiling(const GenLaunch& L, hipStream_t s) {
+    if (L.n_chunks == 0) return hipSuccess;
+    if (L.dtype == kF64) {
+        if (L.spl == 2) return launch_ceiling_t<double, 2>(L, 0.5, s);
+        return launch_ceiling_t<double, 1>(L, 0.5, s);
+    }
+    if (L.spl == 4) return launch_ceiling_t<float, 4>(L, 0.5f, s);
+    if (L.spl == 2) return launch_ceiling_t<float, 2>(L, 0.5f, s);
+    return launch_ceiling_t<float, 1>(L, 0.5f, s);
 }
 
 int batch_kind(int dist, int dtype, int spl) {

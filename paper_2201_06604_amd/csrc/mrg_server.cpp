@@ -118,13 +118,49 @@ struct Lane {
 
 size_t esz_of(mrg_dtype dt) { return dt == MRG_F64 ? 8 : 4; }
 
+// Defaults of the optional configuration fields.
+uint32_t cfg_streams(const mrg_server_cfg& c) { return c.streams_per_session ? c.streams_per_session : 64; }
+uint32_t cfg_lanes(const mrg_server_cfg& c) { return c.mode == 0 ? (c.lanes ? c.lanes : 4) : 0; }
+uint32_t cfg_max_batch(const mrg_server_cfg& c) { return c.max_batch ? c.max_batch : 256; }
+
+// The device workspace a server carves from the caller's buffer: the session
+// stream records, then one batch workspace per lane (sized for max_batch
+// requests, each cut into at most kServeSplit chunks of ceil(S/64) stream
+// blocks), each part 256-byte aligned.
+struct WsLayout {
+    size_t streams_bytes, lane_bytes, total;
+};
+
+WsLayout ws_layout(const mrg_server_cfg& c) {
+    const uint32_t S = cfg_streams(c), mb = cfg_max_batch(c);
+    WsLayout w{};
+    w.streams_bytes = round256(static_cast<size_t>(S) * c.n_sessions * sizeof(mrg_stream));
+    const size_t max_tiles = static_cast<size_t>(mb) * ((S + 63) / 64) * kServeSplit;
+    w.lane_bytes = 256 + round256(mb * sizeof(BatchSlot)) + round256(mb * sizeof(BatchReq)) +
+                   round256(max_tiles * sizeof(BatchTile)) + 1024;
+    w.total = w.streams_bytes + static_cast<size_t>(cfg_lanes(c)) * w.lane_bytes;
+    return w;
+}
+
+// Checks shared by mrg_server_workspace_size and mrg_server_create.
+mrg_status check_cfg(const mrg_server_cfg& c) {
+    if (c.n_sessions == 0) return mrg355_fail(MRG_E_INVALID_ARG, "no sessions");
+    if (c.mode > 1) return mrg355_fail(MRG_E_INVALID_ARG, "mode must be 0 or 1");
+    if (c.lanes > 64) return mrg355_fail(MRG_E_INVALID_ARG, "at most 64 lanes");
+    if (c.max_batch > 65536) return mrg355_fail(MRG_E_INVALID_ARG, "max_batch above 65536");
+    const uint32_t S = cfg_streams(c);
+    if (S > 65536) return mrg355_fail(MRG_E_INVALID_ARG, "streams_per_session above 65536");
+    if (static_cast<uint64_t>(S) * c.n_sessions > (1ull << 31)) return mrg355_fail(MRG_E_INVALID_ARG, "too many streams");
+    return MRG_OK;
+}
+
 }  // namespace
 
 struct mrg_server {
     mrg_server_cfg cfg{};
     uint32_t S = 64;
     int device = 0;
-    uint32_t* streams_dev = nullptr;
+    uint32_t* streams_dev = nullptr;  // in the caller's workspace
     std::vector<uint64_t> sess_off;
     Pool pool;
     std::mutex mu;
@@ -150,6 +186,11 @@ struct mrg_server {
     bool poll_lanes();
     bool poll_plain();
     void complete(uint64_t id, Ticket& t);
+    void note_lanes_busy() {
+        uint64_t busy = 0;
+        for (const Lane& L : lanes) busy += L.busy ? 1 : 0;
+        st.max_lanes_busy = std::max(st.max_lanes_busy, busy);
+    }
     void fail_hip(hipError_t e, const char* what) {
         if (error == MRG_OK) {
             mrg355_fail(MRG_E_HIP, "server %s: %s", what, hipGetErrorString(e));
@@ -282,6 +323,7 @@ bool mrg_server::launch_batch(Lane& L) {
         in_flight += 1;
         st.max_in_flight = std::max<uint64_t>(st.max_in_flight, in_flight);
         ++st.launches;
+        note_lanes_busy();
         return true;
     }
     mrg_batch_plan* plan = nullptr;
@@ -320,6 +362,7 @@ bool mrg_server::launch_batch(Lane& L) {
     in_flight += ids.size();
     st.max_in_flight = std::max<uint64_t>(st.max_in_flight, in_flight);
     ++st.launches;
+    note_lanes_busy();
     return true;
 }
 
@@ -406,7 +449,6 @@ static void destroy_resources(mrg_server* s) {
     for (Lane& L : s->lanes) {
         if (L.stream) (void)hipStreamSynchronize(L.stream);
         if (L.plan) mrg_batch_plan_destroy(L.plan);
-        if (L.ws) (void)hipFree(L.ws);
         if (L.slots_host) (void)hipHostFree(L.slots_host);
         if (L.staging) (void)hipHostFree(L.staging);
         if (L.done_ev) (void)hipEventDestroy(L.done_ev);
@@ -419,59 +461,72 @@ static void destroy_resources(mrg_server* s) {
     for (auto& kv : s->tickets)
         if (kv.second.ev) (void)hipEventDestroy(kv.second.ev);
     for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
-    if (s->streams_dev) (void)hipFree(s->streams_dev);
+}
+
+mrg_status mrg_server_workspace_size(const mrg_server_cfg* cfg, size_t* bytes) {
+    if (!cfg || !bytes) return mrg355_fail(MRG_E_INVALID_ARG, "NULL cfg or bytes");
+    if (mrg_status st = check_cfg(*cfg)) return st;
+    *bytes = ws_layout(*cfg).total;
+    return MRG_OK;
 }
 
 mrg_status mrg_server_create(const mrg_server_cfg* cfg, mrg_server** out) {
     if (!cfg || !out) return mrg355_fail(MRG_E_INVALID_ARG, "NULL cfg or server");
-    if (cfg->n_sessions == 0) return mrg355_fail(MRG_E_INVALID_ARG, "no sessions");
+    if (mrg_status st = check_cfg(*cfg)) return st;
     if (!cfg->pool || cfg->pool_bytes < 256) return mrg355_fail(MRG_E_INVALID_ARG, "no output pool");
     if (reinterpret_cast<uintptr_t>(cfg->pool) % 256) return mrg355_fail(MRG_E_INVALID_ARG, "pool must be 256-byte aligned");
-    if (cfg->mode > 1) return mrg355_fail(MRG_E_INVALID_ARG, "mode must be 0 or 1");
-    if (cfg->lanes > 64) return mrg355_fail(MRG_E_INVALID_ARG, "at most 64 lanes");
-    const uint32_t S = cfg->streams_per_session ? cfg->streams_per_session : 64;
-    if (S > 65536) return mrg355_fail(MRG_E_INVALID_ARG, "streams_per_session above 65536");
-    if (static_cast<uint64_t>(S) * cfg->n_sessions > (1ull << 31))
-        return mrg355_fail(MRG_E_INVALID_ARG, "too many streams");
+    const WsLayout W = ws_layout(*cfg);
+    if (!cfg->workspace) return mrg355_fail(MRG_E_INVALID_ARG, "no device workspace");
+    if (reinterpret_cast<uintptr_t>(cfg->workspace) % 256)
+        return mrg355_fail(MRG_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (cfg->workspace_bytes < W.total)
+        return mrg355_fail(MRG_E_NOMEM, "workspace holds %zu bytes, the server needs %zu", cfg->workspace_bytes,
+                           W.total);
+    {
+        const uintptr_t p0 = reinterpret_cast<uintptr_t>(cfg->pool), p1 = p0 + cfg->pool_bytes;
+        const uintptr_t w0 = reinterpret_cast<uintptr_t>(cfg->workspace), w1 = w0 + W.total;
+        if (p0 < w1 && w0 < p1) return mrg355_fail(MRG_E_INVALID_ARG, "pool and workspace overlap");
+    }
     mrg_creator cr;
     if (mrg_status st = mrg_creator_init(MRG_GEN_MRG32K3A, &cr, cfg->seed)) return st;
 
     mrg_server* s = new (std::nothrow) mrg_server();
     if (!s) return mrg355_fail(MRG_E_NOMEM, "server allocation failed");
     s->cfg = *cfg;
-    s->cfg.streams_per_session = S;
-    if (!s->cfg.lanes) s->cfg.lanes = 4;
-    if (!s->cfg.max_batch) s->cfg.max_batch = 256;
+    s->cfg.streams_per_session = cfg_streams(*cfg);
+    s->cfg.lanes = cfg_lanes(*cfg);
+    s->cfg.max_batch = cfg_max_batch(*cfg);
     if (!s->cfg.tile_units) s->cfg.tile_units = 2048;
+    const uint32_t S = s->cfg.streams_per_session;
     s->S = S;
     s->sess_off.assign(cfg->n_sessions, 0);
     s->pool.init(cfg->pool_bytes);
     hipError_t e = hipGetDevice(&s->device);
 
-    // session streams: session i = streams i*S .. i*S+S-1 of one creator
+    // session streams: session i = streams i*S .. i*S+S-1 of one creator, at
+    // the start of the caller's workspace
+    char* ws = static_cast<char*>(cfg->workspace);
+    s->streams_dev = reinterpret_cast<uint32_t*>(ws);
     const uint64_t n_streams = static_cast<uint64_t>(S) * cfg->n_sessions;
-    if (e == hipSuccess) e = hipMalloc(&s->streams_dev, n_streams * sizeof(mrg_stream));
     if (e == hipSuccess) e = launch_create(kGen32k3a, s->streams_dev, n_streams, cr.s, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
 
-    // lanes: workspace sized for max_batch requests, each cut into at most
-    // kServeSplit chunks of ceil(S/64) stream blocks
-    const size_t max_tiles = static_cast<size_t>(s->cfg.max_batch) * ((S + 63) / 64) * kServeSplit;
-    const size_t ws_bytes = 256 + round256(s->cfg.max_batch * sizeof(BatchSlot)) +
-                            round256(s->cfg.max_batch * sizeof(BatchReq)) + round256(max_tiles * sizeof(BatchTile)) +
-                            1024;
-    const int n_lanes = s->cfg.mode == 0 ? static_cast<int>(s->cfg.lanes) : 0;
-    s->lanes.resize(n_lanes);
-    for (Lane& L : s->lanes) {
+    // lanes: a batch workspace each (device, from the caller's buffer), and
+    // the completion flags and table staging in pinned host memory, which
+    // the library allocates here once
+    s->lanes.resize(s->cfg.lanes);
+    for (size_t i = 0; i < s->lanes.size(); ++i) {
+        Lane& L = s->lanes[i];
         if (e != hipSuccess) break;
-        L.ws_bytes = ws_bytes;
+        L.ws = ws + W.streams_bytes + i * W.lane_bytes;
+        L.ws_bytes = W.lane_bytes;
         e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipMalloc(&L.ws, ws_bytes);
         if (e == hipSuccess)
             e = hipHostMalloc(reinterpret_cast<void**>(&L.slots_host), s->cfg.max_batch * sizeof(BatchSlot),
                               hipHostMallocMapped | hipHostMallocCoherent);
         if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&L.slots_dev), L.slots_host, 0);
-        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&L.staging), ws_bytes, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void**>(&L.staging), W.lane_bytes, hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&L.done_ev, hipEventDisableTiming);
     }
     if (e == hipSuccess && s->cfg.mode == 1) {
@@ -553,10 +608,9 @@ mrg_status mrg_server_poll(mrg_server* s, uint64_t ticket, int* done, void** dev
     if (it == s->tickets.end()) return mrg355_fail(MRG_E_INVALID_ARG, "unknown ticket");
     if (s->error) return mrg355_fail(s->error, "server stopped after an error");
     *done = it->second.state == kDone;
-    if (*done) {
-        if (dev_out) *dev_out = static_cast<char*>(s->cfg.pool) + it->second.pool_off;
-        if (t_done_ns) *t_done_ns = it->second.t_done;
-    }
+    if (!*done) return MRG_E_BUSY;
+    if (dev_out) *dev_out = static_cast<char*>(s->cfg.pool) + it->second.pool_off;
+    if (t_done_ns) *t_done_ns = it->second.t_done;
     return MRG_OK;
 }
 

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
     for name in sorted(declared):
         assert hasattr(L, name), name
     assert set(P.EXPORTED) == declared
-    assert P.mrg_abi_version() == 1
+    assert P.mrg_abi_version() == 2
 
 
 def test_status_strings():
@@ -303,6 +303,8 @@ def test_server_create_validation():
         c.mode = kw.get("mode", 0)
         c.lanes = kw.get("lanes", 0)
         c.streams_per_session = kw.get("sps", 0)
+        c.workspace = kw.get("workspace", 1 << 32)  # never touched: every case fails validation
+        c.workspace_bytes = 1 << 30
         return c
     for bad in [dict(n_sessions=0), dict(pool=0), dict(pool_bytes=16), dict(pool=(1 << 20) + 8),
                 dict(mode=2), dict(lanes=65), dict(sps=70000)]:
@@ -420,3 +422,55 @@ def test_device_creation_size_limit():
 def test_generate_rejects_more_than_2_46_draws_per_stream():
     assert P.mrg_generate_status(256, 1, 1 << 46, P.MRG_UNIFORM, P.MRG_F64, 1.0, 256) == -1
     assert P.mrg_generate_status(256, 4, (1 << 48), P.MRG_UNIFORM, P.MRG_F64, 1.0, 256) == -1
+
+
+def _server_cfg(**kw):
+    cfg = P.mrg_server_cfg()
+    cfg.n_sessions = kw.get("n_sessions", 256)
+    cfg.streams_per_session = kw.get("streams_per_session", 0)
+    for i, v in enumerate(workloads.PAPER_SEED):
+        cfg.seed[i] = v
+    cfg.pool = kw.get("pool", 1 << 40)
+    cfg.pool_bytes = kw.get("pool_bytes", 1 << 30)
+    cfg.lanes, cfg.max_batch, cfg.mode = kw.get("lanes", 0), kw.get("max_batch", 0), kw.get("mode", 0)
+    cfg.workspace = kw.get("workspace", None)
+    cfg.workspace_bytes = kw.get("workspace_bytes", 0)
+    return cfg
+
+
+def test_server_workspace_is_the_callers():
+    """The server's device memory (session streams, lane workspaces) is a
+    caller buffer of mrg_server_workspace_size bytes; a missing, misaligned,
+    short or overlapping one is refused before any HIP call."""
+    L = P.lib()
+    need = ctypes.c_size_t()
+    cfg = _server_cfg()
+    assert L.mrg_server_workspace_size(ctypes.byref(cfg), ctypes.byref(need)) == 0
+    streams = 256 * 64 * 72
+    assert need.value >= streams + 4 * 256 * 16  # records + four lane workspaces
+    plain = _server_cfg(mode=1)
+    n1 = ctypes.c_size_t()
+    assert L.mrg_server_workspace_size(ctypes.byref(plain), ctypes.byref(n1)) == 0
+    assert n1.value == -(-streams // 256) * 256  # mode 1 has no lanes
+    srv = ctypes.c_void_p()
+    for bad, status in [(dict(workspace=None), -1), (dict(workspace=(1 << 41) + 8, workspace_bytes=need.value), -1),
+                        (dict(workspace=1 << 41, workspace_bytes=need.value - 1), -5),
+                        (dict(workspace=(1 << 40) + 4096, workspace_bytes=need.value), -1),
+                        (dict(workspace=1 << 41, workspace_bytes=need.value, n_sessions=0), -1),
+                        (dict(workspace=1 << 41, workspace_bytes=need.value, mode=2), -1)]:
+        c = _server_cfg(**bad)
+        assert L.mrg_server_create(ctypes.byref(c), ctypes.byref(srv)) == status, bad
+        assert not srv.value
+
+
+def test_fisher_rejects_huge_entries_before_summing():
+    """Observed entries whose sum passes 2^31 are refused (grand total above
+    2^20) without overflowing the margin sums first."""
+    L = P.lib()
+    obs = np.array([[2**31 - 1, 2**31 - 1], [5, 5]], dtype=np.int32)
+    cnt = ctypes.c_void_p(256)
+    st = L.mrg_fisher_sim(1, ctypes.c_void_p(256), 10, 2, 2, obs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                          cnt, None, None, None)
+    assert st == -1
+    assert "2^20" in L.mrg_last_error().decode()
+

@@ -4,6 +4,8 @@ States, uniforms (f64, f32 round-toward-zero) and raw integers must match
 bit for bit.  Normals and exponentials must satisfy
 |gpu - ref| <= tol * max(|ref|, 1) with tol = 1e-15 (f64) and 1e-6 (f32).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -317,10 +319,17 @@ def test_reproducible_by_creation_order():
 
 
 # ------------------------------------------------------------ full size
-def test_throughput_config_full_size_sampled():
-    """262,144 streams x 4096 fp64 uniforms (2^30) in the launch shape the
-    benchmark times: every final state, 4096 random streams in full, and the
-    first 16 draws of every stream, bit-exact."""
+FULL_VARIANTS = [(P.MRG_UNIFORM, P.MRG_F64), (P.MRG_UNIFORM, P.MRG_F32), (P.MRG_NORMAL, P.MRG_F64),
+                 (P.MRG_EXPONENTIAL, P.MRG_F64)]
+
+
+@pytest.mark.parametrize("dist,dtype", FULL_VARIANTS, ids=lambda v: str(v))
+def test_throughput_config_full_size_sampled(dist, dtype):
+    """262,144 streams x 4,096 draws (2^30) of every variant the benchmark
+    times (fp64 and fp32 uniforms, fp64 normals, fp64 exponentials), in the
+    launch shape it times: every final state, 4,096 random streams in full,
+    and the first 16 draws of every stream (uniforms bit-exact, transforms
+    within the tolerance)."""
     S, per = 262144, 4096
     seed = workloads.random_seed()
     c = P.mrg_creator_init(seed)
@@ -329,22 +338,43 @@ def test_throughput_config_full_size_sampled():
     rec = O.create_streams(GEN, oc, S)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(P.as_u32(d), rec)
-    out = P.mrg_generate(d, S * per, P.MRG_UNIFORM, P.MRG_F64)
+    out = P.mrg_generate(d, S * per, dist, dtype)
     torch.cuda.synchronize()
     fin = rec[:, 0:6].copy()
-    O.jump_many(GEN, fin, per)
+    O.jump_many(GEN, fin, per)  # 4,096 draws consume 4,096 steps (an even count for normals)
     np.testing.assert_array_equal(P.as_u32(d)[:, 0:6], fin)
     np.testing.assert_array_equal(P.as_u32(d)[:, 6:18], rec[:, 6:18])
     mat = out.view(per, S)
     head = mat[:16].cpu().numpy()
-    want_head = O.generate(GEN, rec.copy(), 16 * S, threads=8).reshape(16, S)
-    assert np.array_equal(head, want_head)
+    want_head = O.generate(GEN, rec.copy(), 16 * S, ODIST[dist], ODT[dtype], threads=8).reshape(16, S)
+    check_values(head.ravel(), want_head.ravel(), dist, dtype, ctx="first 16 draws of every stream")
     rnd = np.random.default_rng(3)
     idx = np.sort(rnd.choice(S, size=4096, replace=False))
     cols = mat[:, torch.from_numpy(idx).cuda()].cpu().numpy()
     sub = rec[idx].copy()
-    want_cols = O.generate(GEN, sub, per * 4096, threads=8).reshape(per, 4096)
-    assert np.array_equal(cols, want_cols)
+    want_cols = O.generate(GEN, sub, per * 4096, ODIST[dist], ODT[dtype], threads=8).reshape(per, 4096)
+    check_values(cols.ravel(), want_cols.ravel(), dist, dtype, ctx="4096 whole streams")
+    del out
+
+
+@pytest.mark.skipif(os.environ.get("MRG_PARITY_LONG") != "1",
+                    reason="long mode: set MRG_PARITY_LONG=1 to compare all 2^30 numbers")
+def test_throughput_config_every_number():
+    """Long mode: all 2^30 fp64 uniforms of the throughput configuration,
+    compared with the oracle in blocks of 16,384 streams (columns of the
+    k*S + s layout)."""
+    S, per, blk = 262144, 4096, 16384
+    seed = workloads.random_seed()
+    c = P.mrg_creator_init(seed)
+    d = P.mrg_streams_create_device(c, S)
+    rec = O.create_streams(GEN, seed.copy(), S)
+    out = P.mrg_generate(d, S * per, P.MRG_UNIFORM, P.MRG_F64)
+    torch.cuda.synchronize()
+    mat = out.view(per, S)
+    for s0 in range(0, S, blk):
+        got = mat[:, s0:s0 + blk].cpu().numpy()
+        want = O.generate(GEN, rec[s0:s0 + blk].copy(), per * blk, threads=16).reshape(per, blk)
+        assert np.array_equal(got, want), f"streams {s0}..{s0 + blk - 1}"
     del out
 
 
@@ -374,3 +404,19 @@ def test_short_buffers_are_rejected_before_launch():
         P.mrg_streams_advance(d[:10], 5, n=11)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(P.as_u32(d), rec)
+
+
+@pytest.mark.parametrize("S,rows,dtype", [(262144, 16, P.MRG_F64), (262144, 24, P.MRG_F32), (1000, 30, P.MRG_F64),
+                                          (131, 7, P.MRG_F32), (64, 3, P.MRG_F64)])
+def test_store_ceiling_writes_exactly_the_output(S, rows, dtype):
+    """The store-only ceiling kernel writes every one of the n elements and
+    nothing past them, in the launch shape mrg_generate would use."""
+    n = S * rows
+    tdt = torch.float64 if dtype == P.MRG_F64 else torch.float32
+    buf = torch.full((n + 64,), -1.0, dtype=tdt, device="cuda")
+    P.mrg_store_ceiling(S, n, dtype, out=buf[:n])
+    torch.cuda.synchronize()
+    assert bool((buf[:n] == 0.5).all())
+    assert bool((buf[n:] == -1.0).all())
+    with pytest.raises(P.MrgError):
+        P.mrg_store_ceiling(S, n + 1, dtype, out=buf)

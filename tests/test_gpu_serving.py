@@ -96,6 +96,8 @@ def test_served_equals_alone(mode, lanes, max_batch):
         srv.release(tk)
     st = srv.stats()
     assert st["completed"] == len(reqs) and st["released"] == len(reqs) and st["pool_in_use"] == 0
+    if mode == 0:  # continuous batching: work of several launches was on the device at once
+        assert st["max_in_flight"] > 1 and st["max_lanes_busy"] >= 2, st
     srv.close()
 
 
@@ -131,6 +133,7 @@ def test_admission_waits_for_memory():
     n = 40000  # 320 KB of f64: three fit
     tks = [srv.submit(i % 4, n)[0] for i in range(20)]
     assert srv.submit_status(0, (1 << 20) // 8 + 64) == -5  # larger than the pool: refused
+    assert srv.poll(tks[-1])[0] is False  # queued behind the pool: MRG_E_BUSY, reported as not done
     done_order = []
     t0 = time.time()
     while len(done_order) < len(tks):

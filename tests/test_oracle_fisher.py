@@ -178,3 +178,71 @@ def test_week_pvalue_near_paper():
         t.join()
     expect = 0.000125 * B
     assert abs(sum(counts) - expect) < 4 * math.sqrt(expect), sum(counts)
+
+
+# ------------------------------------------------------------- the count rule
+def _exact_count(tables, observed):
+    """Replicates whose statistic is at most the observed one, decided exactly:
+    -sum log(n_ij!) <= -sum log(o_ij!)  <=>  prod n_ij! >= prod o_ij!, in
+    Python integers (no rounding anywhere)."""
+    def prod_fact(t):
+        p = 1
+        for v in np.asarray(t).ravel():
+            p *= math.factorial(int(v))
+        return p
+    want = prod_fact(observed)
+    return sum(1 for t in tables if prod_fact(t) >= want)
+
+
+def _replicates(streams, observed):
+    obs = np.asarray(observed, dtype=np.int32)
+    rows, cols = obs.sum(axis=1), obs.sum(axis=0)
+    return [O.table_sample(GEN, streams[b, 0:6].copy(), rows, cols) for b in range(streams.shape[0])]
+
+
+@pytest.mark.parametrize("observed", [[[3, 0, 7, 1]], [[4], [0], [9]], [[17]]])
+def test_determined_tables_count_every_replicate(observed):
+    """Section 4's count is of replicates at most as probable as the observed
+    table.  With one row or one column the margins fix the table, so every
+    replicate equals the observed table and must count: count = B."""
+    B = 300
+    st = O.create_streams(GEN, workloads.random_seed(71), B)
+    cnt, obs_stat = O.fisher_count(GEN, st, np.array(observed, dtype=np.int32))
+    assert cnt == B
+    assert obs_stat == O.table_stat(np.array(observed, dtype=np.int32))
+
+
+def test_ties_count_whatever_the_rounding():
+    """Section 4 counts replicates whose statistic is at most the observed one
+    ("less or equal", as stats::fisher.test to which it compares).  Observed
+    [[2,4],[4,2]]: the replicate [[4,2],[2,4]] has the same statistic
+    mathematically, but its row-major double sum rounds 8.9e-16 above the
+    observed one, so a rule without the near-tie allowance would miss it (and
+    an allowance in the wrong direction would miss the observed table too).
+    With the allowance, '<' and '<=' differ only for a statistic equal to the
+    threshold bit for bit.  The oracle's count must equal the exact count from
+    integer factorials."""
+    obs = np.array([[2, 4], [4, 2]], dtype=np.int32)
+    per = np.array([[4, 2], [2, 4]], dtype=np.int32)
+    assert O.table_stat(per) > O.table_stat(obs)  # the case the allowance exists for
+    B = 4000
+    st = O.create_streams(GEN, workloads.random_seed(72), B)
+    tabs = _replicates(st.copy(), obs)
+    assert sum(1 for t in tabs if np.array_equal(t, per)) > 500
+    assert sum(1 for t in tabs if np.array_equal(t, obs)) > 500
+    cnt, _ = O.fisher_count(GEN, st.copy(), obs)
+    assert cnt == _exact_count(tabs, obs)
+    assert cnt < B  # [[3,3],[3,3]] is more probable and must not count
+
+
+@pytest.mark.parametrize("observed", [[[1, 2, 3], [3, 2, 1]], [[2, 1, 1], [1, 2, 1], [1, 1, 2]],
+                                      [[5, 0], [0, 5]]])
+def test_count_equals_exact_factorial_comparison(observed):
+    """Small tables with many equal-statistic replicates (permutations of the
+    observed entries): the oracle's count equals the exact integer count."""
+    obs = np.array(observed, dtype=np.int32)
+    B = 2500
+    st = O.create_streams(GEN, workloads.random_seed(73 + obs.size), B)
+    tabs = _replicates(st.copy(), obs)
+    cnt, _ = O.fisher_count(GEN, st.copy(), obs)
+    assert cnt == _exact_count(tabs, obs)

@@ -385,3 +385,30 @@ def test_substreams():
     O.reset_stream(U)
     np.testing.assert_array_equal(U[:, 0:6], S[:, 6:12])
     np.testing.assert_array_equal(U[:, 12:18], S[:, 6:12])
+
+
+@pytest.mark.parametrize("comp", [0, 1])
+def test_mrg31k3p_substream_spacing(comp):
+    """MRG31k3p substreams (2^72 apart, the clRNG spacing) tile its streams
+    exactly: (A^(2^72))^(2^62) = A^(2^134), the stream spacing that the
+    stream table printed in Section 2.1 pins; and next_substream is a jump of
+    2^72 steps."""
+    m = MODULI[O.MRG31K3P][comp]
+    K = O.matpow(O.MRG31K3P, comp, 2**72)
+    P = K
+    for _ in range(62):
+        P = _matmul(P, P, m)
+    assert P == O.matpow(O.MRG31K3P, comp, 2**134)
+    assert K != O.matpow(O.MRG31K3P, comp, 2**71) and K != O.matpow(O.MRG31K3P, comp, 2**73)
+
+
+def test_mrg31k3p_next_substream_is_a_2_72_jump():
+    seed = workloads.random_seed(4, gen=O.MRG31K3P)
+    S = O.create_streams(O.MRG31K3P, seed.copy(), 3)
+    T = S.copy()
+    O.next_substream(O.MRG31K3P, T)
+    for i in range(3):
+        s = S[i, 12:18].copy()
+        O.jump(O.MRG31K3P, s, 2**72)
+        np.testing.assert_array_equal(T[i, 12:18], s)
+        np.testing.assert_array_equal(T[i, 0:6], s)
