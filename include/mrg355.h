@@ -374,6 +374,23 @@ mrg_status mrg_batch_upload(const mrg_batch_plan* plan, void* dev_workspace, hip
  * hipGraph and replayed; one workspace serves one launch at a time. */
 mrg_status mrg_batch_launch(const mrg_batch_plan* plan, void* dev_workspace, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under graph capture
+ * without an allocator, tight serving loops, harnesses that forbid hipMalloc):
+ * mrg_batch_upload followed by mrg_batch_launch, with the workspace in a
+ * static device array of the library (MRG_BATCH_STATIC_WORKSPACE_BYTES per
+ * GPU, held until the process ends) instead of a caller buffer.  Enqueues on
+ * `stream`, which must belong to the calling thread's current device: a copy
+ * of the plan's tables into that array, then the launch.  The plan must stay
+ * alive and unchanged until the launch has completed.  Allocates nothing
+ * (no hipMalloc, hipFree, memset or allocating library call).  The array is
+ * shared by every such call on a GPU and keeps the last call's contents (each
+ * launch resets its own counters): calls that may overlap on one GPU race
+ * and must be ordered by the caller (one stream, or events).
+ * MRG_E_NOMEM when the plan's workspace (mrg_batch_workspace_size) exceeds
+ * the array, checked before anything is enqueued. */
+#define MRG_BATCH_STATIC_WORKSPACE_BYTES (16u << 20)
+mrg_status mrg_batch_launch_static(const mrg_batch_plan* plan, hipStream_t stream);
+
 /* After a launch has completed: host_ticks[0] = device real-time clock
  * (100 MHz) when the first tile was taken, host_ticks[1 + r] = when request r
  * finished storing its output (0 if it did not).  n_req + 1 entries.  Copies

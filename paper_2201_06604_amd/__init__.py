@@ -26,6 +26,7 @@ STATUS = {0: "MRG_OK", -1: "MRG_E_INVALID_ARG", -2: "MRG_E_INVALID_SEED", -3: "M
           -4: "MRG_E_HIP", -5: "MRG_E_NOMEM", -6: "MRG_E_CORRUPT_STATE", -7: "MRG_E_BUSY"}
 MRG_CHECK_LOG, MRG_CHECK_SQRT, MRG_CHECK_SINPI, MRG_CHECK_COSPI = 0, 1, 2, 3
 REC_WORDS = 18
+MRG_BATCH_STATIC_WORKSPACE_BYTES = 16 << 20  # mrg_batch_launch_static's device array, per GPU
 
 
 class MrgError(RuntimeError):
@@ -121,6 +122,7 @@ def lib():
             "mrg_batch_tile_count": (i32, [vp, ctypes.POINTER(sz)]),
             "mrg_batch_upload": (i32, [vp, vp, vp]),
             "mrg_batch_launch": (i32, [vp, vp, vp]),
+            "mrg_batch_launch_static": (i32, [vp, vp]),
             "mrg_batch_request_times": (i32, [vp, vp, ctypes.POINTER(ctypes.c_uint64), vp]),
             "mrg_batch_autotune": (i32, [vp, vp, sz, vp, ctypes.POINTER(mrg_batch_cfg),
                                          ctypes.POINTER(ctypes.c_double)]),
@@ -160,7 +162,7 @@ EXPORTED = ["mrg_abi_version", "mrg_status_string", "mrg_last_error", "mrg_seed_
             "mrg_streams_export_size", "mrg_streams_export", "mrg_streams_import",
             "mrg_generate_paper", "mrg_tables_sample", "mrg_fisher_sim", "mrg_fisher_pvalue",
             "mrg_batch_plan_create", "mrg_batch_plan_destroy", "mrg_batch_workspace_size",
-            "mrg_batch_tile_count", "mrg_batch_upload", "mrg_batch_launch",
+            "mrg_batch_tile_count", "mrg_batch_upload", "mrg_batch_launch", "mrg_batch_launch_static",
             "mrg_batch_request_times", "mrg_batch_autotune", "mrg_batch_autotune_workspace_size",
             "mrg_transform_accuracy", "mrg_store_ceiling",
             "mrg_now_ns", "mrg_server_workspace_size", "mrg_server_create",
@@ -505,6 +507,11 @@ class BatchPlan:
 
     def launch(self, stream=None):
         _check(lib().mrg_batch_launch(self._p, ctypes.c_void_p(self._ws_ptr), _stream(stream)))
+
+    def launch_static(self, stream=None):
+        """Upload and launch with the library's static device workspace (no
+        allocation anywhere; the plan must outlive the launch)."""
+        _check(lib().mrg_batch_launch_static(self._p, _stream(stream)))
 
     def request_times(self, stream=None):
         """Device real-time clock ticks (100 MHz): [start, done_0, ..., done_{n-1}]."""

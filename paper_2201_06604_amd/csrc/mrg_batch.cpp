@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -267,6 +268,39 @@ mrg_status launch(const mrg_batch_plan& P, void* ws, hipStream_t stream, BatchSl
 
 }  // namespace
 
+// Workspace of mrg_batch_launch_static, for callers that cannot allocate
+// device memory.  Each GPU the library runs on holds its own copy for the life
+// of the process; host code reaches it only through the device address that
+// hipGetSymbolAddress returns for that GPU (the array's name is a host-side
+// stand-in, not a device address).
+static __device__ __align__(256) char scratch[MRG_BATCH_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` per GPU, looked up once
+
+// The device address of `scratch` on the calling thread's current GPU.
+mrg_status static_workspace(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return mrg355_fail(MRG_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return mrg355_fail(MRG_E_UNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return mrg355_fail(MRG_E_HIP, "static workspace address: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MRG_OK;
+}
+
+}  // namespace
+
 namespace mrg355 {
 
 // Plans for the serving engine: requests already validated, optionally
@@ -383,6 +417,23 @@ mrg_status mrg_batch_launch(const mrg_batch_plan* plan, void* dev_workspace, hip
     if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
         return mrg355_fail(MRG_E_INVALID_ARG, "workspace must be 256-byte aligned");
     return launch(*plan, dev_workspace, stream);
+}
+
+mrg_status mrg_batch_launch_static(const mrg_batch_plan* plan, hipStream_t stream) {
+    if (!plan) return mrg355_fail(MRG_E_INVALID_ARG, "NULL plan");
+    if (plan->bytes > MRG_BATCH_STATIC_WORKSPACE_BYTES)
+        return mrg355_fail(MRG_E_NOMEM,
+                           "the plan needs %zu bytes of workspace, the static workspace holds %zu: "
+                           "use mrg_batch_launch with a workspace of its own",
+                           plan->bytes, static_cast<size_t>(MRG_BATCH_STATIC_WORKSPACE_BYTES));
+    void* ws = nullptr;
+    if (mrg_status st = static_workspace(&ws)) return st;
+    if (!plan->packed.empty()) {
+        hipError_t e = hipMemcpyAsync(static_cast<char*>(ws) + plan->off_reqs, plan->packed.data(),
+                                      plan->packed.size(), hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return mrg355_fail(MRG_E_HIP, "static batch upload: %s", hipGetErrorString(e));
+    }
+    return launch(*plan, ws, stream);
 }
 
 mrg_status mrg_batch_request_times(const mrg_batch_plan* plan, const void* dev_workspace,

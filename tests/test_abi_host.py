@@ -474,3 +474,16 @@ def test_fisher_rejects_huge_entries_before_summing():
     assert st == -1
     assert "2^20" in L.mrg_last_error().decode()
 
+
+
+def test_static_batch_rejects_a_plan_above_its_workspace():
+    """mrg_batch_launch_static refuses, before touching HIP, a plan whose
+    workspace exceeds the library's static array (2^20 one-unit tiles need
+    more than 16 MiB); the pointers are never dereferenced."""
+    req = P.mrg_request(1 << 40, 64, 64 << 20, P.MRG_UNIFORM, P.MRG_F64, 1.0, 1 << 44)
+    plan = P.BatchPlan([req], cfg=dict(tile_units=1))
+    assert plan.workspace_size() > P.MRG_BATCH_STATIC_WORKSPACE_BYTES
+    with pytest.raises(P.MrgError) as e:
+        plan.launch_static(stream=0)
+    assert e.value.status == -5
+    assert "static workspace" in str(e.value)
