@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MRG_ABI_VERSION 2
+#define MRG_ABI_VERSION 3
 
 typedef enum {
     MRG_OK = 0,
@@ -285,20 +285,27 @@ double     mrg_fisher_pvalue(uint64_t count, uint64_t B);
  * Section 3.1) and exponential (Section 3.2) transforms evaluate them with the
  * library's own code, which leaves out the range reduction and special cases
  * of the general functions (a uniform lies in [2^-33, 1) and is never zero,
- * subnormal or non-finite). */
+ * subnormal or non-finite).  Draws stored as MRG_F32 use shorter evaluations
+ * of the same functions (the _F32OUT entries: about 1e-7 relative, since the
+ * result is rounded to float). */
 typedef enum {
     MRG_CHECK_LOG = 0,    /* log(u), u = z/(m1+1): exponential draws, Box-Muller radius */
     MRG_CHECK_SQRT = 1,   /* sqrt(x), x = -2 log(u): the Box-Muller radius R          */
     MRG_CHECK_SINPI = 2,  /* sin(pi t), t = 2u: the Box-Muller angle                   */
-    MRG_CHECK_COSPI = 3   /* cos(pi t), t = 2u                                         */
+    MRG_CHECK_COSPI = 3,  /* cos(pi t), t = 2u                                         */
+    MRG_CHECK_LOG_F32OUT = 4,    /* the same four, as the fp32 outputs evaluate them */
+    MRG_CHECK_SQRT_F32OUT = 5,
+    MRG_CHECK_SINPI_F32OUT = 6,
+    MRG_CHECK_COSPI_F32OUT = 7
 } mrg_check_fn;
 
 /* For every integer z in [z_begin, z_end), the generator output a step can
  * produce (1 <= z_begin <= z_end <= m1 + 1), evaluate function `fn` at the
  * input that z gives the transforms, once with the library's code and once
- * with the HIP device math library (log, sqrt, sincospi; MRG_CHECK_SQRT feeds
- * both the library's -2 log(u)), and count how many doubles apart the two
- * results are.  dev_result (device, 8 uint64, 8-byte aligned) receives:
+ * with the HIP device math library (log, sqrt, sincospi; the square root
+ * checks feed both the library's full-precision -2 log(u)), and count how
+ * many doubles apart the two results are (a relative error e is about
+ * e * 2^52 to e * 2^53 doubles).  dev_result (device, 8 uint64, 8-byte aligned) receives:
  * [0]..[3] the number of inputs 0, 1, 2, 3 apart, [4] 4 or more apart,
  * [5] (largest distance << 32) | the largest z at that distance (distance
  * capped at 2^32 - 1), [6] and [7] zero.  The call clears dev_result itself
@@ -342,12 +349,20 @@ typedef struct {
  *   tile_units      most draws (normal: pairs) one wave makes in one tile
  *   waves_per_simd  waves per SIMD of the persistent grid (1..16), capped at
  *                   what the kernel's registers allow to be resident at once
- *   wide_stores     0 = automatic (16-byte stores where a request allows),
- *                   1 = force one stream per lane                        */
+ *   wide_stores     0 = automatic (stores up to 16 bytes wide where a
+ *                   request allows, unless a narrower width leaves fewer
+ *                   lanes idle), 1 = force one stream per lane
+ *   gang_waves      1 = every wave takes tiles on its own, from one queue per
+ *                   class (normal, exponential, uniform/raw); 2, 4 or 8 = a
+ *                   block of that many waves takes a gang of that many tiles
+ *                   -- neighbouring stream blocks of one request -- and its
+ *                   waves write each row together (a barrier per row), from
+ *                   one queue that interleaves the classes              */
 typedef struct {
     uint32_t tile_units;
     uint32_t waves_per_simd;
     uint32_t wide_stores;
+    uint32_t gang_waves;
 } mrg_batch_cfg;
 
 typedef struct mrg_batch_plan mrg_batch_plan;  /* opaque, owned by the library */
@@ -398,8 +413,9 @@ mrg_status mrg_batch_launch_static(const mrg_batch_plan* plan, hipStream_t strea
 mrg_status mrg_batch_request_times(const mrg_batch_plan* plan, const void* dev_workspace,
                                    uint64_t* host_ticks, hipStream_t stream);
 
-/* Autotuner: time candidate shapes (tile_units in {512, ..., 16384} x
- * waves_per_simd in {2, 3, 4}) of the plan on the GPU with its own requests,
+/* Autotuner: time candidate shapes (tile_units in {512, ..., 8192} x
+ * gang_waves in {1, 4, 8} x wide_stores in {0, 1} x waves_per_simd in
+ * {2, 3, 4}) of the plan on the GPU with its own requests,
  * in `dev_workspace` (capacity `workspace_bytes`; shapes whose workspace would
  * not fit are skipped: mrg_batch_autotune_workspace_size gives the capacity
  * that fits every candidate), keep

@@ -25,6 +25,7 @@ MRG_E_BUSY = -7
 STATUS = {0: "MRG_OK", -1: "MRG_E_INVALID_ARG", -2: "MRG_E_INVALID_SEED", -3: "MRG_E_UNSUPPORTED",
           -4: "MRG_E_HIP", -5: "MRG_E_NOMEM", -6: "MRG_E_CORRUPT_STATE", -7: "MRG_E_BUSY"}
 MRG_CHECK_LOG, MRG_CHECK_SQRT, MRG_CHECK_SINPI, MRG_CHECK_COSPI = 0, 1, 2, 3
+MRG_CHECK_LOG_F32OUT, MRG_CHECK_SQRT_F32OUT, MRG_CHECK_SINPI_F32OUT, MRG_CHECK_COSPI_F32OUT = 4, 5, 6, 7
 REC_WORDS = 18
 MRG_BATCH_STATIC_WORKSPACE_BYTES = 16 << 20  # mrg_batch_launch_static's device array, per GPU
 
@@ -65,7 +66,7 @@ class mrg_request(ctypes.Structure):
 
 class mrg_batch_cfg(ctypes.Structure):
     _fields_ = [("tile_units", ctypes.c_uint32), ("waves_per_simd", ctypes.c_uint32),
-                ("wide_stores", ctypes.c_uint32)]
+                ("wide_stores", ctypes.c_uint32), ("gang_waves", ctypes.c_uint32)]
 
 
 class mrg_server_cfg(ctypes.Structure):
@@ -470,7 +471,8 @@ class BatchPlan:
         arr = (mrg_request * max(len(requests), 1))(*requests)
         c = None if cfg is None else ctypes.byref(mrg_batch_cfg(cfg.get("tile_units", 0),
                                                                 cfg.get("waves_per_simd", 0),
-                                                                cfg.get("wide_stores", 0)))
+                                                                cfg.get("wide_stores", 0),
+                                                                cfg.get("gang_waves", 0)))
         self._p = ctypes.c_void_p()
         _check(lib().mrg_batch_plan_create(gen, arr, len(requests), c, ctypes.byref(self._p)))
         self.n_req = len(requests)
@@ -537,7 +539,7 @@ class BatchPlan:
         _check(lib().mrg_batch_autotune(self._p, ctypes.c_void_p(self._ws_ptr), self._ws_bytes,
                                         _stream(stream), ctypes.byref(best), ctypes.byref(ms)))
         return dict(tile_units=best.tile_units, waves_per_simd=best.waves_per_simd,
-                    wide_stores=best.wide_stores), ms.value
+                    wide_stores=best.wide_stores, gang_waves=best.gang_waves), ms.value
 
 
 # ------------------------------------------------------------------ serving

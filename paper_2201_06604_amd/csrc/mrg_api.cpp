@@ -379,7 +379,7 @@ double mrg_fisher_pvalue(uint64_t count, uint64_t B) {
 mrg_status mrg_transform_accuracy(mrg_generator gen, mrg_check_fn fn, uint64_t z_begin, uint64_t z_end,
                                   uint64_t* dev_result, hipStream_t stream) {
     if (mrg_status st = check_gen(gen)) return st;
-    if (fn != MRG_CHECK_LOG && fn != MRG_CHECK_SQRT && fn != MRG_CHECK_SINPI && fn != MRG_CHECK_COSPI)
+    if (static_cast<int>(fn) < MRG_CHECK_LOG || static_cast<int>(fn) > MRG_CHECK_COSPI_F32OUT)
         return fail(MRG_E_INVALID_ARG, "unknown function %d", static_cast<int>(fn));
     const uint64_t m1 = gen == MRG_GEN_MRG32K3A ? kM1 : kP1;
     if (z_begin < 1 || z_begin > z_end || z_end > m1 + 1)

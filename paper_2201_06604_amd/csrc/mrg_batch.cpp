@@ -31,10 +31,12 @@ struct mrg_batch_plan {
     uint32_t tile_units;
     uint32_t waves_per_simd;
     uint32_t wide;
+    uint32_t gang;  // 1 = class queues of wave tiles; 2, 4, 8 = gangs of that many waves
     std::vector<BatchReq> reqs;
     std::vector<BatchTile> tiles;
     uint32_t tile_lo[kClasses + 1];
     double cls_cost[kClasses];
+    uint32_t n_gangs;  // gang mode: tiles holds n_gangs * gang entries (padding: req = kNoRequest)
     std::vector<uint32_t> fin_req;
     std::vector<uint64_t> fin_pre;
     uint64_t fin_total;
@@ -46,6 +48,7 @@ namespace {
 
 constexpr uint32_t kDefaultTileUnits = 4096;
 constexpr uint32_t kDefaultWavesPerSimd = 8;
+constexpr uint32_t kDefaultGang = 1;
 constexpr unsigned kBatchBlock = 256;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -116,6 +119,66 @@ void pack_tables(mrg_batch_plan& P) {
     put(P.off_fin_pre, P.fin_pre.data(), P.fin_pre.size() * sizeof(uint64_t));
 }
 
+// Gang mode: within each class, tiles longest first and, among tiles of equal
+// length, in (request, chunk, stream block) order, so that a gang -- G
+// consecutive tiles -- holds neighbouring stream blocks of one request and
+// chunk wherever the request has them; the last gang of a class is padded.
+// The classes' gangs are then merged into one queue by the share of their
+// class's estimated work done at each gang's midpoint, so that every class
+// advances at the same pace and all of them finish together.
+void order_gangs(mrg_batch_plan& P, const std::vector<double>& cost, const std::vector<uint64_t>& len) {
+    const uint32_t G = P.gang;
+    std::vector<uint32_t> by_cls[kClasses];
+    for (uint32_t t = 0; t < P.tiles.size(); ++t)
+        by_cls[batch_kind_class(static_cast<int>(P.reqs[P.tiles[t].req].kind))].push_back(t);
+    struct Gang {
+        double key;
+        int cls;
+        uint32_t first;  // index into `member`
+    };
+    std::vector<Gang> gangs;
+    std::vector<uint32_t> member;  // tile indices, G per gang, kNoRequest for padding
+    for (int c = 0; c < kClasses; ++c) {
+        std::vector<uint32_t>& v = by_cls[c];
+        std::stable_sort(v.begin(), v.end(), [&](uint32_t a, uint32_t b) { return len[a] > len[b]; });
+        const size_t n_g = (v.size() + G - 1) / G;
+        std::vector<double> gcost(n_g, 0.0);
+        double total = 0.0;
+        for (size_t g = 0; g < n_g; ++g) {
+            for (uint32_t w = 0; w < G; ++w) {
+                const size_t k = g * G + w;
+                if (k < v.size()) gcost[g] = std::max(gcost[g], cost[v[k]]);
+            }
+            total += gcost[g];
+        }
+        double done = 0.0;
+        for (size_t g = 0; g < n_g; ++g) {
+            gangs.push_back(Gang{total > 0 ? (done + 0.5 * gcost[g]) / total : 0.0, c,
+                                 static_cast<uint32_t>(member.size())});
+            done += gcost[g];
+            for (uint32_t w = 0; w < G; ++w) {
+                const size_t k = g * G + w;
+                member.push_back(k < v.size() ? v[k] : kNoRequest);
+            }
+        }
+    }
+    std::stable_sort(gangs.begin(), gangs.end(), [](const Gang& a, const Gang& b) {
+        if (a.key != b.key) return a.key < b.key;
+        return a.cls < b.cls;
+    });
+    std::vector<BatchTile> out;
+    out.reserve(gangs.size() * G);
+    for (const Gang& g : gangs)
+        for (uint32_t w = 0; w < G; ++w) {
+            const uint32_t t = member[g.first + w];
+            out.push_back(t == kNoRequest ? BatchTile{kNoRequest, 0, 0, 0} : P.tiles[t]);
+        }
+    P.tiles.swap(out);
+    P.n_gangs = static_cast<uint32_t>(gangs.size());
+    for (int c = 0; c <= kClasses; ++c) P.tile_lo[c] = 0;
+    for (int c = 0; c < kClasses; ++c) P.cls_cost[c] = 0.0;
+}
+
 // (Re)cut the plan's requests into tiles for its tile_units / wide setting.
 mrg_status build(mrg_batch_plan& P) {
     P.reqs.clear();
@@ -123,6 +186,7 @@ mrg_status build(mrg_batch_plan& P) {
     P.fin_req.clear();
     P.fin_pre.assign(1, 0);
     std::vector<double> cost;
+    std::vector<uint64_t> len;  // draw units of each tile
     for (size_t i = 0; i < P.user.size(); ++i) {
         const mrg_request& q = P.user[i].q;
         BatchReq R{};
@@ -143,6 +207,20 @@ mrg_status build(mrg_batch_plan& P) {
         while (spl > 1 && (q.n_streams % spl || reinterpret_cast<uintptr_t>(q.out) % (spl * esz))) spl /= 2;
         while (spl > 1 && 64ull * spl > q.n_streams) spl /= 2;  // a wave's streams must exist
         if (esz == 4 && spl == 2) spl = 1;  // tiles of 4-byte outputs use 1 or 4 streams per lane
+        if (P.wide == 0) {
+            // a wave covers 64 * spl streams and issues its instructions for
+            // all of them: keep the narrowest width that leaves the fewest
+            // lanes idle in the request's last stream block (S = 300: one
+            // stream per lane, 320 lane slots, rather than four, 512)
+            auto slots = [&](int v) {
+                const uint64_t w = 64ull * static_cast<uint64_t>(v);
+                return (static_cast<uint64_t>(q.n_streams) + w - 1) / w * w;
+            };
+            int best = spl;
+            for (int v = spl / 2; v >= 1; v /= 2)
+                if (!(esz == 4 && v == 2) && slots(v) < slots(best)) best = v;
+            spl = best;
+        }
         L.spl = spl;
         R.kind = static_cast<uint32_t>(batch_kind(L.dist, L.dtype, spl));
         if (q.n == 0) {
@@ -172,6 +250,7 @@ mrg_status build(mrg_batch_plan& P) {
                 P.tiles.push_back(BatchTile{static_cast<uint32_t>(i), static_cast<uint32_t>(sb),
                                             static_cast<uint32_t>(j), 0});
                 cost.push_back(static_cast<double>(u) * unit_cost(L.dist, L.dtype) * 64 * spl);
+                len.push_back(u);
             }
         if (n_chunks > 1 && !L.no_writeback) {
             P.fin_req.push_back(static_cast<uint32_t>(i));
@@ -179,6 +258,10 @@ mrg_status build(mrg_batch_plan& P) {
         }
         P.reqs.push_back(R);
     }
+    P.n_gangs = 0;
+    if (P.gang > 1) {
+        order_gangs(P, cost, len);
+    } else {
     // grouped by class (normal, exponential, uniform/raw), longest first
     // within a class; ties keep request order
     std::vector<uint32_t> order(P.tiles.size());
@@ -199,6 +282,7 @@ mrg_status build(mrg_batch_plan& P) {
     std::vector<BatchTile> sorted(P.tiles.size());
     for (size_t i = 0; i < order.size(); ++i) sorted[i] = P.tiles[order[i]];
     P.tiles.swap(sorted);
+    }
     P.fin_total = P.fin_pre.back();
     // workspace layout
     const size_t n_req = P.reqs.size();
@@ -225,6 +309,7 @@ BatchLaunch launch_args(const mrg_batch_plan& P, void* ws) {
     B.n_tiles = static_cast<uint32_t>(P.tiles.size());
     B.n_fin = static_cast<uint32_t>(P.fin_req.size());
     B.fin_total = P.fin_total;
+    B.n_gangs = P.n_gangs;
     for (int c = 0; c <= kClasses; ++c) B.tile_lo[c] = P.tile_lo[c];
     return B;
 }
@@ -241,6 +326,17 @@ mrg_status launch(const mrg_batch_plan& P, void* ws, hipStream_t stream, BatchSl
     if (P.tiles.empty() && P.reqs.empty()) return MRG_OK;
     BatchLaunch B = launch_args(P, ws);
     B.host_slots = host_slots;
+    if (P.n_gangs) {
+        // one queue of gangs; the grid is what is resident at once at the
+        // requested waves per SIMD, and no larger than the gang count
+        const unsigned block = 64 * P.gang;
+        const uint64_t per_cu = std::min<uint64_t>(static_cast<uint64_t>(batch_gang_blocks_per_cu(block)),
+                                                   std::max<uint64_t>(1, 4 * P.waves_per_simd / P.gang));
+        const uint64_t grid = std::min<uint64_t>(static_cast<uint64_t>(device_cu_count()) * per_cu, P.n_gangs);
+        hipError_t e = launch_batch(B, static_cast<unsigned>(grid), block, stream);
+        if (e != hipSuccess) return mrg355_fail(MRG_E_HIP, "batch launch: %s", hipGetErrorString(e));
+        return MRG_OK;
+    }
     // The grid is at most what is resident at once, shared between the class
     // loops in proportion to the estimated work (a class with tiles gets at
     // least one block and at most one per 4 of its tiles); blocks move on to
@@ -313,6 +409,7 @@ mrg_status plan_internal(const std::vector<PlanReq>& reqs, uint32_t tile_units, 
     P->tile_units = tile_units;
     P->waves_per_simd = 4;
     P->wide = 0;
+    P->gang = 1;
     mrg_status st = build(*P);
     if (st) {
         delete P;
@@ -346,6 +443,9 @@ mrg_status mrg_batch_plan_create(mrg_generator gen, const mrg_request* reqs, siz
     if (n_req > 0xfffffffful) return mrg355_fail(MRG_E_INVALID_ARG, "too many requests");
     if (cfg && cfg->waves_per_simd > 16) return mrg355_fail(MRG_E_INVALID_ARG, "waves_per_simd above 16");
     if (cfg && cfg->wide_stores > 1) return mrg355_fail(MRG_E_INVALID_ARG, "wide_stores must be 0 or 1");
+    if (cfg && cfg->gang_waves && cfg->gang_waves != 1 && cfg->gang_waves != 2 && cfg->gang_waves != 4 &&
+        cfg->gang_waves != 8)
+        return mrg355_fail(MRG_E_INVALID_ARG, "gang_waves must be 0, 1, 2, 4 or 8");
     std::vector<std::pair<uintptr_t, uintptr_t>> sr, orng;
     for (size_t i = 0; i < n_req; ++i) {
         if (mrg_status st = validate_request(reqs[i], i)) return st;
@@ -365,6 +465,7 @@ mrg_status mrg_batch_plan_create(mrg_generator gen, const mrg_request* reqs, siz
     P->tile_units = (cfg && cfg->tile_units) ? cfg->tile_units : kDefaultTileUnits;
     P->waves_per_simd = (cfg && cfg->waves_per_simd) ? cfg->waves_per_simd : kDefaultWavesPerSimd;
     P->wide = cfg ? cfg->wide_stores : 0;
+    P->gang = (cfg && cfg->gang_waves) ? cfg->gang_waves : kDefaultGang;
     mrg_status st = build(*P);
     if (st) {
         delete P;
@@ -382,19 +483,29 @@ mrg_status mrg_batch_workspace_size(const mrg_batch_plan* plan, size_t* bytes) {
     return MRG_OK;
 }
 
-// Shapes the autotuner times: tile_units x waves per SIMD.
-static constexpr uint32_t kTuneTileUnits[] = {512, 1024, 2048, 4096, 8192, 16384};
+// Shapes the autotuner times: tile length (draw units per wave tile) x block
+// shape (class queues of single waves, or gangs of 4 or 8 waves) x streams per
+// lane (widest stores a request allows, or one stream per lane) x waves per
+// SIMD.  Tile length sets the per-stream work-item count (a stream of u units
+// is cut into ceil(u / tile_units) work-items).
+static constexpr uint32_t kTuneTileUnits[] = {512, 1024, 2048, 4096, 8192};
+static constexpr uint32_t kTuneGang[] = {1, 4, 8};
+static constexpr uint32_t kTuneWide[] = {0, 1};
 static constexpr uint32_t kTuneWaves[] = {2, 3, 4};
 
 mrg_status mrg_batch_autotune_workspace_size(const mrg_batch_plan* plan, size_t* bytes) {
     if (!plan || !bytes) return mrg355_fail(MRG_E_INVALID_ARG, "NULL plan or bytes");
     size_t most = plan->bytes;
-    for (uint32_t tu : kTuneTileUnits) {
-        mrg_batch_plan trial = *plan;
-        trial.tile_units = tu;
-        if (mrg_status st = build(trial)) return st;
-        most = std::max(most, trial.bytes);
-    }
+    for (uint32_t tu : kTuneTileUnits)
+        for (uint32_t g : kTuneGang)
+            for (uint32_t w : kTuneWide) {
+                mrg_batch_plan trial = *plan;
+                trial.tile_units = tu;
+                trial.gang = g;
+                trial.wide = w;
+                if (mrg_status st = build(trial)) return st;
+                most = std::max(most, trial.bytes);
+            }
     *bytes = most;
     return MRG_OK;
 }
@@ -471,36 +582,43 @@ mrg_status mrg_batch_autotune(mrg_batch_plan* plan, void* dev_workspace, size_t 
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return mrg355_fail(MRG_E_HIP, "autotune save: %s", hipGetErrorString(e));
 
-    const uint32_t orig_tu = plan->tile_units, orig_w = plan->waves_per_simd;
+    const uint32_t orig_tu = plan->tile_units, orig_w = plan->waves_per_simd, orig_g = plan->gang,
+                   orig_wide = plan->wide;
     double best_t = 1e30;
-    uint32_t best_tu = orig_tu, best_w = orig_w;
+    uint32_t best_tu = orig_tu, best_w = orig_w, best_g = orig_g, best_wide = orig_wide;
     hipEvent_t a = nullptr, b = nullptr;
     e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
     mrg_status st = MRG_OK;
-    for (uint32_t tu : kTuneTileUnits) {
-        if (st || e != hipSuccess) break;
-        plan->tile_units = tu;
-        if ((st = build(*plan))) break;
-        if (plan->bytes > workspace_bytes) continue;  // does not fit the caller's workspace
-        if ((st = upload(*plan, dev_workspace, stream))) break;
-        for (uint32_t w : kTuneWaves) {
-            plan->waves_per_simd = w;
-            if ((st = launch(*plan, dev_workspace, stream))) break;  // warm-up
-            e = hipEventRecord(a, stream);
-            for (int rep = 0; rep < 3 && !st; ++rep) st = launch(*plan, dev_workspace, stream);
-            if (e == hipSuccess) e = hipEventRecord(b, stream);
-            if (e == hipSuccess) e = hipEventSynchronize(b);
-            float ms = 0;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-            if (st || e != hipSuccess) break;
-            if (ms / 3 < best_t) {
-                best_t = ms / 3;
-                best_tu = tu;
-                best_w = w;
+    for (uint32_t tu : kTuneTileUnits)
+        for (uint32_t g : kTuneGang)
+            for (uint32_t wide : kTuneWide) {
+                if (st || e != hipSuccess) break;
+                plan->tile_units = tu;
+                plan->gang = g;
+                plan->wide = wide;
+                if ((st = build(*plan))) break;
+                if (plan->bytes > workspace_bytes) continue;  // does not fit the caller's workspace
+                if ((st = upload(*plan, dev_workspace, stream))) break;
+                for (uint32_t w : kTuneWaves) {
+                    plan->waves_per_simd = w;
+                    if ((st = launch(*plan, dev_workspace, stream))) break;  // warm-up
+                    e = hipEventRecord(a, stream);
+                    for (int rep = 0; rep < 3 && !st; ++rep) st = launch(*plan, dev_workspace, stream);
+                    if (e == hipSuccess) e = hipEventRecord(b, stream);
+                    if (e == hipSuccess) e = hipEventSynchronize(b);
+                    float ms = 0;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+                    if (st || e != hipSuccess) break;
+                    if (ms / 3 < best_t) {
+                        best_t = ms / 3;
+                        best_tu = tu;
+                        best_w = w;
+                        best_g = g;
+                        best_wide = wide;
+                    }
+                }
             }
-        }
-    }
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
     // restore the streams, keep the best shape
@@ -510,8 +628,11 @@ mrg_status mrg_batch_autotune(mrg_batch_plan* plan, void* dev_workspace, size_t 
                            stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    plan->tile_units = best_t < 1e30 ? best_tu : orig_tu;
-    plan->waves_per_simd = best_t < 1e30 ? best_w : orig_w;
+    const bool found = best_t < 1e30;
+    plan->tile_units = found ? best_tu : orig_tu;
+    plan->waves_per_simd = found ? best_w : orig_w;
+    plan->gang = found ? best_g : orig_g;
+    plan->wide = found ? best_wide : orig_wide;
     mrg_status st2 = build(*plan);
     if (st) return st;
     if (e != hipSuccess) return mrg355_fail(MRG_E_HIP, "autotune: %s", hipGetErrorString(e));
@@ -522,6 +643,7 @@ mrg_status mrg_batch_autotune(mrg_batch_plan* plan, void* dev_workspace, size_t 
         best->tile_units = plan->tile_units;
         best->waves_per_simd = plan->waves_per_simd;
         best->wide_stores = plan->wide;
+        best->gang_waves = plan->gang;
     }
     if (best_ms) *best_ms = best_t < 1e30 ? best_t : 0.0;
     return MRG_OK;

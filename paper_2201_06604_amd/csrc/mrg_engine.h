@@ -312,6 +312,80 @@ __device__ __forceinline__ double log_unit(double u) {
     return __builtin_fma(kd, kLn2Hi * SCALE, __builtin_fma(kd, kLn2Lo * SCALE, log_m));
 }
 
+// ----------------------------------------------- transforms for fp32 output
+// A normal or exponential draw stored as a float needs its value to about
+// 1e-7 relative, not to the last bit of a double, so these evaluate the same
+// formulas with shorter series and no refinement of the hardware estimates.
+// Their results are rounded to float.  Each function's relative error
+// (bounds below, checked over every generator output by
+// mrg_transform_accuracy) stays under 2e-7.  The largest error of a stored
+// float is then under 4e-7 of max(|value|, 1), against the 1e-6 fp32
+// tolerance.
+
+// log(u) as log_unit, but s = f * rcp(d) with the hardware reciprocal alone
+// (relative error below 2^-23 on these divisors), and atanh(s) through s^7.
+// The truncation adds below 2|s| (s^2)^4 / 9 < 3e-8.  Near u = 1 (k = 0)
+// both errors are relative to log(u) itself, so the result keeps ~1e-7
+// relative accuracy where log(u) is tiny.
+template <int SCALE = 1>
+__device__ __forceinline__ double log_unit_f32out(double u) {
+    static_assert(SCALE == 1 || SCALE == -1 || SCALE == 2 || SCALE == -2, "power-of-two scale");
+    int k = __builtin_amdgcn_frexp_exp(u);
+    double m = __builtin_amdgcn_frexp_mant(u);
+    const int lo = m < 0.70710678118654752440 ? 1 : 0;
+    m = __builtin_amdgcn_ldexp(m, lo);
+    k -= lo;
+    const double f = m - 1.0;
+    const double q = f * __builtin_amdgcn_rcp(2.0 + f);  // s = f / (2 + f)
+    const double z = q * q;
+    double r = 1.0 / 7.0;
+    r = __builtin_fma(r, z, 1.0 / 5.0);
+    r = __builtin_fma(r, z, 1.0 / 3.0);
+    r = r * z;
+    const double s2 = q * (2.0 * SCALE);
+    const double log_m = __builtin_fma(s2, r, s2);
+    constexpr double kLn2 = 6.93147180559945286227e-01;
+    return __builtin_fma(static_cast<double>(k), kLn2 * SCALE, log_m);
+}
+
+// sqrt(x) for the radius argument, x in [2^-32, 47]: the hardware reciprocal
+// square root and one Newton correction of g = x y (relative error of the
+// order of the estimate's square, far below 1e-7).
+__device__ __forceinline__ double sqrt_radius_f32out(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double g = x * y;
+    const double d = __builtin_fma(-g, g, x);
+    return __builtin_fma(d, 0.5 * y, g);
+}
+
+// sin(pi t), cos(pi t) as sincospi_unit, with the Taylor series cut at r^9
+// (sine) and r^10 (cosine): at |r| = 1/4 the next terms are below 2e-9 and
+// 2e-10.
+__device__ __forceinline__ void sincospi_unit_f32out(double t, double* sp, double* cp) {
+    const double n = __builtin_rint(t + t);
+    const double r = __builtin_fma(n, -0.5, t);
+    const double z = r * r;
+    double ps = 0.08214588661112823;
+    ps = __builtin_fma(ps, z, -0.5992645293207921);
+    ps = __builtin_fma(ps, z, 2.5501640398773455);
+    ps = __builtin_fma(ps, z, -5.16771278004997);
+    ps = __builtin_fma(ps, z, 3.141592653589793);
+    const double sn = r * ps;
+    double pc = -0.02580689139001406;
+    pc = __builtin_fma(pc, z, 0.2353306303588932);
+    pc = __builtin_fma(pc, z, -1.3352627688545895);
+    pc = __builtin_fma(pc, z, 4.0587121264167685);
+    pc = __builtin_fma(pc, z, -4.934802200544679);
+    const double cs = __builtin_fma(pc, z, 1.0);
+    const uint32_t ni = static_cast<uint32_t>(static_cast<int>(n));
+    const double s1 = (ni & 1u) ? cs : sn;
+    const double c1 = (ni & 1u) ? sn : cs;
+    const uint32_t sgn_s = (ni << 30) & 0x80000000u;
+    const uint32_t sgn_c = ((ni + 1u) << 30) & 0x80000000u;
+    *sp = __hiloint2double(__double2hiint(s1) ^ static_cast<int>(sgn_s), __double2loint(s1));
+    *cp = __hiloint2double(__double2hiint(c1) ^ static_cast<int>(sgn_c), __double2loint(c1));
+}
+
 __device__ __forceinline__ double to_f64(uint32_t z) { return static_cast<double>(z); }
 __device__ __forceinline__ double to_f64(double z) { return z; }
 __device__ __forceinline__ uint32_t to_u32(uint32_t z) { return z; }

@@ -51,6 +51,7 @@ struct BatchReq {       // one request, static for a plan
 struct BatchTile {      // a wave's unit of work
     uint32_t req, sblk, chunk, pad;
 };
+constexpr uint32_t kNoRequest = 0xffffffffu;  // BatchTile.req of the padding of a short gang
 
 struct BatchSlot {      // per-request counters, reset by every launch
     uint32_t remaining; // tiles not finished
@@ -85,9 +86,12 @@ struct BatchLaunch {    // kernel arguments
     uint32_t block_lo[kClasses + 1];  // and blocks [block_lo[c], block_lo[c+1])
     uint32_t wpb;                     // waves per block of the persistent kernel
     uint64_t fin_total;
+    uint32_t n_gangs;                 // gang mode: tiles[g*wpb .. g*wpb+wpb-1] is gang g; 0 = class queues
+    uint32_t grid;                    // blocks of the persistent kernel
 };
 
 hipError_t launch_batch(const BatchLaunch& B, unsigned grid, unsigned block, hipStream_t s);
+int batch_gang_blocks_per_cu(unsigned block);
 
 }  // namespace mrg355
 

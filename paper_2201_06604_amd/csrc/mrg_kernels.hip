@@ -101,9 +101,8 @@ __device__ __forceinline__ typename ElemOf<DTYPE>::T value1(Z z, double inv_rate
     } else {
         double u = to_f64(z) * norm_of<G>();
         if constexpr (DIST == kExponential) {
-            double v = -log_unit(u) * inv_rate;
-            if constexpr (DTYPE == kF64) return v;
-            else return static_cast<float>(v);
+            if constexpr (DTYPE == kF64) return -log_unit(u) * inv_rate;
+            else return static_cast<float>(-log_unit_f32out(u) * inv_rate);
         } else {
             return u;
         }
@@ -113,13 +112,20 @@ __device__ __forceinline__ typename ElemOf<DTYPE>::T value1(Z z, double inv_rate
 // Box-Muller pair (Algorithm 1) from two consecutive steps of one stream.
 // The factors -2 and 2 are folded into exact power-of-two scalings: -2 log(u1)
 // comes from log_unit<-2>, and 2 u2 = z2 (2 NORM) is the same double as
-// 2 (z2 NORM).
-template <int G, typename Z>
+// 2 (z2 NORM).  A pair stored as floats (DTYPE kF32) takes the shorter
+// evaluations of the same functions.
+template <int G, int DTYPE, typename Z>
 __device__ __forceinline__ void box_muller(Z z1, Z z2, double& x, double& y) {
     const double u1 = to_f64(z1) * norm_of<G>();
-    const double r = sqrt_radius(log_unit<-2>(u1));
-    double s, c;
-    sincospi_unit(to_f64(z2) * (2.0 * norm_of<G>()), &s, &c);
+    const double t = to_f64(z2) * (2.0 * norm_of<G>());
+    double r, s, c;
+    if constexpr (DTYPE == kF64) {
+        r = sqrt_radius(log_unit<-2>(u1));
+        sincospi_unit(t, &s, &c);
+    } else {
+        r = sqrt_radius_f32out(log_unit_f32out<-2>(u1));
+        sincospi_unit_f32out(t, &s, &c);
+    }
     x = r * c;
     y = r * s;
 }
@@ -190,8 +196,12 @@ __device__ __forceinline__ void main_rows(const GenLaunch& L, uint32_t by, uint6
 // SPL values of a draw index with one SPL*esz-byte store.
 // One wave's share of one request: stream block `sblk` (64*SPL streams),
 // draw units [by*chunk, (by+1)*chunk).  Wave-uniform arguments.
-template <int DIST, int DTYPE, int ARITH, int SPL, bool NT, bool LOCK = false>
+// LOCK: workgroup barriers per unrolled main-loop iteration (three rows, or
+// three pairs for normals): 0, 1 (after the iteration) or 3 (after every row
+// or pair).
+template <int DIST, int DTYPE, int ARITH, int SPL, bool NT, int LOCK = 0>
 __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uint32_t by) {
+    static_assert(LOCK == 0 || LOCK == 1 || LOCK == 3, "barriers per iteration");
     using Engine = typename std::conditional<
         ARITH == kArith31, Engine31,
         typename std::conditional<ARITH == kArithF64, F64Engine, IntEngine>::type>::type;
@@ -256,24 +266,25 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
             row += rowstep;
             store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, py);
             row += rowstep;
-            if constexpr (LOCK) __builtin_amdgcn_s_barrier();
+            if constexpr (LOCK == 3) __builtin_amdgcn_s_barrier();
         };
         for (; k + 3 <= kend; k += 3) {
             pair([](Engine& g, double& x, double& y) {
                 auto z0 = g.template step<0>();
                 auto z1 = g.template step<1>();
-                box_muller<G>(z0, z1, x, y);
+                box_muller<G, DTYPE>(z0, z1, x, y);
             });
             pair([](Engine& g, double& x, double& y) {
                 auto z2 = g.template step<2>();
                 auto z3 = g.template step<0>();
-                box_muller<G>(z2, z3, x, y);
+                box_muller<G, DTYPE>(z2, z3, x, y);
             });
             pair([](Engine& g, double& x, double& y) {
                 auto z4 = g.template step<1>();
                 auto z5 = g.template step<2>();
-                box_muller<G>(z4, z5, x, y);
+                box_muller<G, DTYPE>(z4, z5, x, y);
             });
+            if constexpr (LOCK == 1) __builtin_amdgcn_s_barrier();
         }
         for (; k < kend; ++k) {
             Pack<T, SPL> px, py;
@@ -282,7 +293,7 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
                 auto z0 = e[i].step_rot();
                 auto z1 = e[i].step_rot();
                 double x, y;
-                box_muller<G>(z0, z1, x, y);
+                box_muller<G, DTYPE>(z0, z1, x, y);
                 px.v[i] = narrow<DTYPE>(x);
                 py.v[i] = narrow<DTYPE>(y);
             }
@@ -300,7 +311,7 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
                     auto z0 = e[i].step_rot();
                     auto z1 = e[i].step_rot();
                     double x, y;
-                    box_muller<G>(z0, z1, x, y);
+                    box_muller<G, DTYPE>(z0, z1, x, y);
                     if (2 * k < cnt[i]) store_1<T, NT>(row_rsrc(row, nrec), voff + i * ESZ, narrow<DTYPE>(x));
                     if (2 * k + 1 < cnt[i])
                         store_1<T, NT>(row_rsrc(row + rowstep, nrec), voff + i * ESZ, narrow<DTYPE>(y));
@@ -319,13 +330,13 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
             }
             store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, p0);
             row += rowstep;
-            if constexpr (LOCK) __builtin_amdgcn_s_barrier();
+            if constexpr (LOCK == 3) __builtin_amdgcn_s_barrier();
             store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, p1);
             row += rowstep;
-            if constexpr (LOCK) __builtin_amdgcn_s_barrier();
+            if constexpr (LOCK == 3) __builtin_amdgcn_s_barrier();
             store_n<T, SPL, NT>(row_rsrc(row, nrec), voff, p2);
             row += rowstep;
-            if constexpr (LOCK) __builtin_amdgcn_s_barrier();
+            if constexpr (LOCK != 0) __builtin_amdgcn_s_barrier();
         }
         for (; k < kend; ++k) {
             Pack<T, SPL> p;
@@ -393,7 +404,7 @@ __global__ void __launch_bounds__(1024) gen_kernel(GenLaunch L) {
         }
         return;
     }
-    run_chunk<DIST, DTYPE, ARITH, SPL, NT, LOCK>(L, sblk, by);
+    run_chunk<DIST, DTYPE, ARITH, SPL, NT, LOCK ? 3 : 0>(L, sblk, by);
 }
 
 // cur <- A^(steps consumed) cur for every stream, after a chunked launch:
@@ -420,7 +431,11 @@ __global__ void __launch_bounds__(256) finalize_kernel(uint32_t* streams, uint32
 // kernel (no memset node, so the launch can be captured in a graph).
 __global__ void __launch_bounds__(256) batch_init_kernel(BatchLaunch B) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
+    if (i == 0 && B.n_gangs) {
+        // gang mode: block b starts on gang b, the queue hands out the rest
+        B.head->queue[0] = B.grid;
+        B.head->t_start = 0;
+    } else if (i == 0) {
         // tiles [0, waves of the class) are taken without the queue (each
         // wave's first tile in its own class); the queue hands out the rest
         for (int c = 0; c < kClasses; ++c) {
@@ -454,6 +469,32 @@ __device__ __forceinline__ void batch_tile(const GenLaunch& L, uint32_t sblk, ui
     if constexpr (KIND == kBNormF32) run_chunk<kNormal, kF32, kArithF64, 1, false>(L, sblk, chunk);
     if constexpr (KIND == kBExpF64) run_chunk<kExponential, kF64, kArithF64, 1, false>(L, sblk, chunk);
     if constexpr (KIND == kBExpF32) run_chunk<kExponential, kF32, kArithF64, 1, false>(L, sblk, chunk);
+}
+
+// A wave has stored its tile of request `req`: count the tile off the request;
+// the wave that finishes the request stamps the device real-time clock into its
+// slot.  `one` is 1 on lane 0 and 0 elsewhere (every lane executes the atomic).
+__device__ __forceinline__ void finish_tile(const BatchLaunch& B, uint32_t req, uint32_t one) {
+    // The count must follow this wave's stores.  When a host thread watches
+    // completions (serving), it may hand a finished output to other work while
+    // this kernel still runs: the stores are released device-wide (an L2
+    // write-back on this chip).  Otherwise consumers are ordered after the
+    // launch, whose end makes everything visible, and waiting for the stores
+    // to complete is enough.
+    if (B.host_slots) __threadfence();
+    else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    const uint32_t left = __builtin_amdgcn_readfirstlane(atomicSub(&B.slots[req].remaining, one));
+    if (left == 1) {  // wave-uniform: this wave finished the request
+        const uint64_t t_done = __builtin_amdgcn_s_memrealtime();
+        B.slots[req].t_done = t_done;
+        __threadfence();
+        B.slots[req].done = 1;
+        if (B.host_slots) {  // tell a polling host thread
+            B.host_slots[req].t_done = t_done;
+            __threadfence_system();
+            B.host_slots[req].done = 1;
+        }
+    }
 }
 
 // Persistent kernel.  Tiles come in three classes with separate queues:
@@ -507,26 +548,7 @@ __device__ __forceinline__ void batch_worker(const BatchLaunch& B, uint32_t firs
                 default: batch_tile<kBRawU32x4>(L, sblk, chunk); break;
             }
         }
-        // The count must follow this wave's stores.  When a host thread
-        // watches completions (serving), it may hand a finished output to
-        // other work while this kernel still runs: the stores are released
-        // device-wide (an L2 write-back on this chip).  Otherwise consumers
-        // are ordered after the launch, whose end makes everything visible,
-        // and waiting for the stores to complete is enough.
-        if (B.host_slots) __threadfence();
-        else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        const uint32_t left = __builtin_amdgcn_readfirstlane(atomicSub(&B.slots[req].remaining, one));
-        if (left == 1) {  // wave-uniform: this wave finished the request
-            const uint64_t t_done = __builtin_amdgcn_s_memrealtime();
-            B.slots[req].t_done = t_done;
-            __threadfence();
-            B.slots[req].done = 1;
-            if (B.host_slots) {  // tell a polling host thread
-                B.host_slots[req].t_done = t_done;
-                __threadfence_system();
-                B.host_slots[req].done = 1;
-            }
-        }
+        finish_tile(B, req, one);
     }
 }
 
@@ -558,6 +580,112 @@ __global__ void __launch_bounds__(256) batch_kernel(BatchLaunch B) {
         batch_worker<kClsPlain>(B, home_rank(B, kClsPlain));
         batch_worker<kClsNormal>(B, kNone);
         batch_worker<kClsExp>(B, kNone);
+    }
+}
+
+// ---------------------------------------------------------- gang batching
+// A gang is G wave tiles (G = waves per block) that one block runs together:
+// wave w takes tile w of the gang, and the waves pass a workgroup barrier after
+// every row (pair, for normals) of their main loops.  The host puts consecutive
+// stream blocks of one request and chunk in a gang, so the row segments of
+// neighbouring waves -- which share a cache line wherever a row does not start
+// on a 128-byte line -- are written within a few rows of each other and the
+// line is completed in this CU's L2 instead of reaching HBM in two partial
+// writes.  Every wave passes as many barriers as the gang's longest main loop
+// (each wave works out every tile's count with the rule run_chunk follows).
+// Gangs of every class share one queue, which the host interleaves so that the
+// classes advance at the same pace: transform-heavy and store-heavy tiles run
+// side by side throughout the launch and finish together.
+#ifndef MRG_GANG_LOCK
+#define MRG_GANG_LOCK 3
+#endif
+constexpr int kGangLock = MRG_GANG_LOCK;  // barriers per unrolled main-loop iteration (1 or 3)
+
+template <int KIND>
+__device__ __forceinline__ void gang_tile(const GenLaunch& L, uint32_t sblk, uint32_t chunk) {
+    if constexpr (KIND == kBUniF64x1) run_chunk<kUniform, kF64, kArithF64, 1, false, kGangLock>(L, sblk, chunk);
+    if constexpr (KIND == kBUniF64x2) run_chunk<kUniform, kF64, kArithF64, 2, false, kGangLock>(L, sblk, chunk);
+    if constexpr (KIND == kBUniF32x1) run_chunk<kUniform, kF32, kArithF64, 1, false, kGangLock>(L, sblk, chunk);
+    if constexpr (KIND == kBUniF32x4) run_chunk<kUniform, kF32, kArithF64, 4, false, kGangLock>(L, sblk, chunk);
+    if constexpr (KIND == kBRawU32x1) run_chunk<kRaw, kU32, kArithF64, 1, false, kGangLock>(L, sblk, chunk);
+    if constexpr (KIND == kBRawU32x4) run_chunk<kRaw, kU32, kArithF64, 4, false, kGangLock>(L, sblk, chunk);
+    if constexpr (KIND == kBNormF64) run_chunk<kNormal, kF64, kArithF64, 1, false, kGangLock>(L, sblk, chunk);
+    if constexpr (KIND == kBNormF32) run_chunk<kNormal, kF32, kArithF64, 1, false, kGangLock>(L, sblk, chunk);
+    if constexpr (KIND == kBExpF64) run_chunk<kExponential, kF64, kArithF64, 1, false, kGangLock>(L, sblk, chunk);
+    if constexpr (KIND == kBExpF32) run_chunk<kExponential, kF32, kArithF64, 1, false, kGangLock>(L, sblk, chunk);
+}
+
+// Main-loop iterations of a wave tile: run_chunk passes kGangLock barriers
+// per iteration, and its main loop runs floor((kend - u0) / 3) of them, with u0
+// and kend as main_rows gives them (0 for the padding of a short gang).  Every
+// operand is wave-uniform.
+__device__ __forceinline__ uint32_t tile_iters(const BatchLaunch& B, const BatchTile& T) {
+    const uint32_t req = __builtin_amdgcn_readfirstlane(T.req);
+    if (req == kNoRequest) return 0;
+    const GenLaunch& L = B.reqs[req].L;
+    const uint32_t chunk = __builtin_amdgcn_readfirstlane(T.chunk);
+    uint64_t u0, u1, kend;
+    if (L.dist == kNormal) main_rows<kNormal>(L, chunk, u0, u1, kend);
+    else main_rows<kUniform>(L, chunk, u0, u1, kend);
+    return __builtin_amdgcn_readfirstlane(static_cast<uint32_t>((kend - u0) / 3));
+}
+
+// Blocks take gangs from one counter (the first gang of block b is b).  The
+// gang index travels through LDS: wave 0 takes it (every lane executes the
+// atomic, increment 1 on lane 0 only), and two barriers bracket the read so
+// that no wave can overwrite it before every wave has read it.  All control
+// flow around the barriers is block-uniform.
+__global__ void __launch_bounds__(512) batch_gang_kernel(BatchLaunch B) {
+    __shared__ uint32_t next_gang;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t one = lane == 0 ? 1u : 0u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (blockIdx.x == 0 && threadIdx.x < 64) B.head->t_start = __builtin_amdgcn_s_memrealtime();
+    uint32_t g = blockIdx.x;
+    while (g < B.n_gangs) {
+        const BatchTile* gt = B.tiles + static_cast<uint64_t>(g) * B.wpb;
+        uint32_t nbar = 0, nit = 0;
+        for (uint32_t w = 0; w < B.wpb; ++w) {
+            const uint32_t it = tile_iters(B, gt[w]);
+            nbar = it > nbar ? it : nbar;
+            if (w == wave) nit = it;
+        }
+        const uint32_t req = __builtin_amdgcn_readfirstlane(gt[wave].req);
+        if (req != kNoRequest) {
+            const uint32_t sblk = __builtin_amdgcn_readfirstlane(gt[wave].sblk);
+            const uint32_t chunk = __builtin_amdgcn_readfirstlane(gt[wave].chunk);
+            const uint32_t kind = __builtin_amdgcn_readfirstlane(B.reqs[req].kind);
+            const GenLaunch& L = B.reqs[req].L;
+            switch (kind) {
+                case kBUniF64x1: gang_tile<kBUniF64x1>(L, sblk, chunk); break;
+                case kBUniF64x2: gang_tile<kBUniF64x2>(L, sblk, chunk); break;
+                case kBUniF32x1: gang_tile<kBUniF32x1>(L, sblk, chunk); break;
+                case kBUniF32x4: gang_tile<kBUniF32x4>(L, sblk, chunk); break;
+                case kBRawU32x1: gang_tile<kBRawU32x1>(L, sblk, chunk); break;
+                case kBRawU32x4: gang_tile<kBRawU32x4>(L, sblk, chunk); break;
+                case kBNormF64: gang_tile<kBNormF64>(L, sblk, chunk); break;
+                case kBNormF32: gang_tile<kBNormF32>(L, sblk, chunk); break;
+                case kBExpF64: gang_tile<kBExpF64>(L, sblk, chunk); break;
+                default: gang_tile<kBExpF32>(L, sblk, chunk); break;
+            }
+            finish_tile(B, req, one);
+        }
+        // the barriers of the gang's longer main loops (kGangLock per
+        // unrolled iteration, as run_chunk passes them)
+        for (uint32_t i = nit; i < nbar; ++i) {
+            __builtin_amdgcn_s_barrier();
+            if constexpr (kGangLock == 3) {
+                __builtin_amdgcn_s_barrier();
+                __builtin_amdgcn_s_barrier();
+            }
+        }
+        if (wave == 0) {
+            const uint32_t q = __builtin_amdgcn_readfirstlane(atomicAdd(&B.head->queue[0], one));
+            next_gang = q;
+        }
+        __syncthreads();
+        g = next_gang;
+        __syncthreads();
     }
 }
 
@@ -969,6 +1097,22 @@ hipError_t launch_store_ceiling(const GenLaunch& L, hipStream_t s) {
     return launch_ceiling_t<float, 1>(L, 0.5f, s);
 }
 
+int batch_gang_blocks_per_cu(unsigned block) {
+    static std::mutex mu;
+    static int cached[9] = {0};  // by waves per block
+    const unsigned w = block / 64;
+    if (w == 0 || w > 8) return 1;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!cached[w]) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(batch_gang_kernel),
+                                                         static_cast<int>(block), 0) != hipSuccess || n <= 0)
+            n = 1;
+        cached[w] = n;
+    }
+    return cached[w];
+}
+
 int batch_kind(int dist, int dtype, int spl) {
     switch (dist) {
         case kUniform:
@@ -1004,10 +1148,12 @@ int device_cu_count() {
 hipError_t launch_batch(const BatchLaunch& B_in, unsigned grid, unsigned block, hipStream_t s) {
     BatchLaunch B = B_in;
     B.wpb = block / 64;
+    B.grid = grid;
     hipLaunchKernelGGL(batch_init_kernel, dim3(grid1d(B.n_req ? B.n_req : 1, 256)), dim3(256), 0, s, B);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), 0, s, B);
+    if (B.n_gangs) hipLaunchKernelGGL(batch_gang_kernel, dim3(grid), dim3(block), 0, s, B);
+    else hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), 0, s, B);
     e = hipGetLastError();
     if (e != hipSuccess || B.fin_total == 0) return e;
     hipLaunchKernelGGL(batch_finalize_kernel, dim3(static_cast<unsigned>((B.fin_total + 255) / 256)),
@@ -1098,7 +1244,7 @@ __global__ void __launch_bounds__(256) paper_kernel(PaperLaunch L) {
                 auto z1 = ea.step_rot();
                 auto z2 = eb.step_rot();
                 double xv, yv;
-                box_muller<G>(z1, z2, xv, yv);
+                box_muller<G, DTYPE>(z1, z2, xv, yv);
                 __builtin_nontemporal_store(narrow<DTYPE>(xv), row + c);
                 __builtin_nontemporal_store(narrow<DTYPE>(yv), row + c + 1);
             } else {

@@ -36,16 +36,18 @@ __device__ __forceinline__ uint64_t distance_at(int fn, uint64_t z) {
     constexpr double norm = G == kGen32k3a ? kNorm : kNorm31;
     const double u = static_cast<double>(z) * norm;
     if (fn == MRG_CHECK_LOG) return ulp_distance(log_unit(u), log(u));
-    if (fn == MRG_CHECK_SQRT) {
+    if (fn == MRG_CHECK_LOG_F32OUT) return ulp_distance(log_unit_f32out(u), log(u));
+    if (fn == MRG_CHECK_SQRT || fn == MRG_CHECK_SQRT_F32OUT) {
         const double x = log_unit<-2>(u);  // the Box-Muller radius argument
-        return ulp_distance(sqrt_radius(x), sqrt(x));
+        return ulp_distance(fn == MRG_CHECK_SQRT ? sqrt_radius(x) : sqrt_radius_f32out(x), sqrt(x));
     }
     // the Box-Muller angle argument 2u, formed as the kernels form it
     const double t = static_cast<double>(z) * (2.0 * norm);
     double s, c, s_ref, c_ref;
-    sincospi_unit(t, &s, &c);
+    if (fn == MRG_CHECK_SINPI || fn == MRG_CHECK_COSPI) sincospi_unit(t, &s, &c);
+    else sincospi_unit_f32out(t, &s, &c);
     sincospi(t, &s_ref, &c_ref);
-    return fn == MRG_CHECK_SINPI ? ulp_distance(s, s_ref) : ulp_distance(c, c_ref);
+    return (fn == MRG_CHECK_SINPI || fn == MRG_CHECK_SINPI_F32OUT) ? ulp_distance(s, s_ref) : ulp_distance(c, c_ref);
 }
 
 __global__ void __launch_bounds__(64) accuracy_clear_kernel(unsigned long long* res) {

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
     for name in sorted(declared):
         assert hasattr(L, name), name
     assert set(P.EXPORTED) == declared
-    assert P.mrg_abi_version() == 2
+    assert P.mrg_abi_version() == 3
 
 
 def test_status_strings():
@@ -271,18 +271,27 @@ def test_batch_plan_validation():
 
 def test_batch_tiles_cover_requests():
     """Tile counts follow the cut: ceil(S / (64*SPL)) stream blocks times
-    ceil(units / tile_units) chunks, summed over requests."""
+    ceil(units / tile_units) chunks, summed over requests.  SPL is the widest
+    store the request allows unless a narrower one leaves fewer lane slots
+    idle (S = 130: two streams per lane would cover 256, one covers 192)."""
     base = 1 << 20
-    S1, n1 = 130, 130 * 1000 + 7          # f64 uniform, S even -> 2 streams/lane
+    S1, n1 = 130, 130 * 1000 + 7          # f64 uniform: 1 stream/lane, 3 blocks
     S2, n2 = 77, 77 * 301                 # normal, 1 stream/lane, pairs = 151
+    S3, n3 = 256, 256 * 250               # f64 uniform: 2 streams/lane, 2 blocks
     reqs = [_req(base, S1, n1, out=1 << 32),
-            _req(base + S1 * 72, S2, n2, dist=1, out=(1 << 33))]
+            _req(base + S1 * 72, S2, n2, dist=1, out=(1 << 33)),
+            _req(base + (S1 + S2) * 72, S3, n3, out=(1 << 34))]
     st, plan = _plan_status(reqs, (100, 0, 0))
     assert st == 0
     nt = ctypes.c_size_t()
     P.lib().mrg_batch_tile_count(plan, ctypes.byref(nt))
-    want = 2 * ((1001 + 99) // 100) + 2 * ((151 + 99) // 100)
+    want = 3 * ((1001 + 99) // 100) + 2 * ((151 + 99) // 100) + 2 * ((250 + 99) // 100)
     assert nt.value == want
+    P.lib().mrg_batch_plan_destroy(plan)
+    st, plan = _plan_status(reqs, (100, 0, 1))  # one stream per lane everywhere
+    assert st == 0
+    P.lib().mrg_batch_tile_count(plan, ctypes.byref(nt))
+    assert nt.value == 3 * 11 + 2 * 2 + 4 * 3
     P.lib().mrg_batch_plan_destroy(plan)
 
 
@@ -487,3 +496,21 @@ def test_static_batch_rejects_a_plan_above_its_workspace():
         plan.launch_static(stream=0)
     assert e.value.status == -5
     assert "static workspace" in str(e.value)
+
+
+def test_batch_gang_plans():
+    """Gang plans (blocks of 2, 4 or 8 waves taking neighbouring tiles
+    together) hold a whole number of gangs; other gang sizes are refused."""
+    base = 1 << 20
+    reqs = [_req(base, 131, 131 * 5000, out=1 << 30), _req(base + 131 * 72, 64, 64 * 7, dist=1, out=1 << 31),
+            _req(base + 195 * 72, 1000, 1000 * 3001, dtype=1, out=1 << 32)]
+    for g in (2, 4, 8):
+        st, plan = _plan_status(reqs, (512, 0, 0, g))
+        assert st == 0
+        n = ctypes.c_size_t()
+        assert P.lib().mrg_batch_tile_count(plan, ctypes.byref(n)) == 0
+        assert n.value % g == 0 and n.value > 0
+        P.lib().mrg_batch_plan_destroy(plan)
+    for g in (3, 5, 16):
+        st, _ = _plan_status(reqs, (512, 0, 0, g))
+        assert st == -1

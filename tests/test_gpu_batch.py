@@ -122,7 +122,12 @@ def test_batch_equals_plain_equals_oracle():
 
 @pytest.mark.parametrize("cfg", [dict(tile_units=1), dict(tile_units=7, waves_per_simd=1),
                                  dict(tile_units=64, wide_stores=1), dict(tile_units=100000),
-                                 dict(waves_per_simd=16), dict(tile_units=333, waves_per_simd=2)],
+                                 dict(waves_per_simd=16), dict(tile_units=333, waves_per_simd=2),
+                                 dict(gang_waves=4), dict(gang_waves=2, tile_units=7),
+                                 dict(gang_waves=8, tile_units=333, waves_per_simd=2),
+                                 dict(gang_waves=4, tile_units=1, waves_per_simd=1),
+                                 dict(gang_waves=8, tile_units=64, wide_stores=1),
+                                 dict(gang_waves=2, tile_units=100000, waves_per_simd=16)],
                          ids=str)
 def test_batch_shape_invariance(cfg):
     A, B = Mix(MIX, 1), Mix(MIX, 1)
@@ -154,11 +159,12 @@ def test_batch_relaunch_continues_streams():
         assert torch.equal(A.streams[i], B.streams[i])
 
 
-def test_batch_graph_replay_matches_eager():
+@pytest.mark.parametrize("gang", [1, 4])
+def test_batch_graph_replay_matches_eager(gang):
     """Capture one launch in a HIP graph, replay it three times with eager
     work in between; each replay must equal the matching eager launch."""
     A, B = Mix(MIX, 3), Mix(MIX, 3)
-    planA = P.BatchPlan(A.requests(), dict(tile_units=200))
+    planA = P.BatchPlan(A.requests(), dict(tile_units=200, gang_waves=gang))
     planA.upload()
     planB = P.BatchPlan(B.requests(), dict(tile_units=200))
     planB.upload()
@@ -194,7 +200,8 @@ def test_batch_autotune_leaves_streams_and_stays_exact():
     before = [t.clone() for t in A.streams]
     best, ms = plan.autotune()
     assert plan.workspace_size() <= plan._ws_bytes
-    assert best["tile_units"] in (512, 1024, 2048, 4096, 8192, 16384) and best["waves_per_simd"] in (2, 3, 4)
+    assert best["tile_units"] in (512, 1024, 2048, 4096, 8192) and best["waves_per_simd"] in (2, 3, 4)
+    assert best["gang_waves"] in (1, 4, 8) and best["wide_stores"] in (0, 1)
     assert ms > 0
     for a, b in zip(A.streams, before):
         assert torch.equal(a, b)
@@ -207,7 +214,8 @@ def test_batch_autotune_leaves_streams_and_stays_exact():
         assert torch.equal(A.streams[i], B.streams[i])
 
 
-def test_batched_config_full_size():
+@pytest.mark.parametrize("cfg", [None, dict(tile_units=1024, waves_per_simd=2, gang_waves=4)], ids=str)
+def test_batched_config_full_size(cfg):
     """4096 requests, lengths log-uniform in [1e3, 1e7], 64-1024 streams each,
     random mix of f32/f64 and uniform/normal/exponential: the batch equals
     4096 plain launches bit for bit (outputs and states); sampled requests
@@ -228,7 +236,8 @@ def test_batched_config_full_size():
         outsA.append(oA)
         creqs.append(P.make_request(sA, r["n"], dist, dtype, 1.0, oA))
         meta.append((r, dist, dtype))
-    plan = P.BatchPlan(creqs)
+    print(f"full-size batch, cfg {cfg}", flush=True)
+    plan = P.BatchPlan(creqs, cfg)
     plan.upload()
     plan.launch()
     torch.cuda.synchronize()

@@ -156,6 +156,41 @@ def test_transcendentals_every_output(gen, fn):
             run(gen, rec, 3 * len(triples), P.MRG_NORMAL, dtype, 1.0)
 
 
+FNS32 = {P.MRG_CHECK_LOG_F32OUT: "log", P.MRG_CHECK_SQRT_F32OUT: "sqrt", P.MRG_CHECK_SINPI_F32OUT: "sinpi",
+         P.MRG_CHECK_COSPI_F32OUT: "cospi"}
+
+
+@pytest.mark.parametrize("fn", list(FNS32), ids=lambda f: FNS32[f] + "_f32out")
+@pytest.mark.parametrize("gen", GENS)
+def test_f32out_transcendentals_every_output(gen, fn):
+    """The shorter evaluations that fp32 normals and exponentials use stay
+    within 2e-7 relative of the HIP device math library over every z in
+    [1, m1]: d doubles apart is at most d * 2^-52 relative.  Rounded to
+    float (2^-24 relative) the stored value is then within 3e-7 of the exact
+    one, against the 1e-6 fp32 tolerance; at the worst input the fp32
+    transforms match the oracle within that tolerance."""
+    m1 = C.modulus1(gen)
+    r = P.mrg_transform_accuracy(fn, gen=gen)
+    rel = r["max_ulp"] * 2.0 ** -52
+    print(f"gen={gen} {FNS32[fn]} f32out: max {r['max_ulp']} doubles apart (<= {rel:.3e} relative) "
+          f"at z={r['z_at_max']}")
+    assert sum(r["hist"]) == m1
+    assert rel <= 2e-7, r
+    z = r["z_at_max"]
+    assert 1 <= z <= m1
+    rng = np.random.default_rng(z % 1000003)
+    other = lambda: int(rng.integers(1, m1 + 1))  # noqa: E731
+    if fn in (P.MRG_CHECK_LOG_F32OUT, P.MRG_CHECK_SQRT_F32OUT):
+        triples = [(z, other(), z), (z, z, other())]
+        rec = crafted_records(gen, triples, z)
+        run(gen, rec, 3 * len(triples), P.MRG_NORMAL, P.MRG_F32, 1.0)
+        run(gen, rec, 3 * len(triples), P.MRG_EXPONENTIAL, P.MRG_F32, 1.0)
+    else:
+        triples = [(other(), z, other()), (1, z, other()), (m1, z, other())]
+        rec = crafted_records(gen, triples, z)
+        run(gen, rec, 3 * len(triples), P.MRG_NORMAL, P.MRG_F32, 1.0)
+
+
 def test_transform_accuracy_partial_range_and_errors():
     """A sub-range counts exactly its inputs; bad ranges are refused."""
     r = P.mrg_transform_accuracy(P.MRG_CHECK_LOG, 1000, 1000 + 12345)
@@ -165,3 +200,5 @@ def test_transform_accuracy_partial_range_and_errors():
     for lo, hi in ((0, 10), (10, 5), (1, 4294967087 + 2)):
         with pytest.raises(P.MrgError):
             P.mrg_transform_accuracy(P.MRG_CHECK_LOG, lo, hi)
+    with pytest.raises(P.MrgError):
+        P.mrg_transform_accuracy(8, 1, 10)
