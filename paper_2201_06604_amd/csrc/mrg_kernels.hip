@@ -29,6 +29,7 @@
 #include "mrg_engine.h"
 #include "mrg_internal.h"
 #include "mrg_math.h"
+#include "mrg_tuned.h"
 
 namespace mrg355 {
 
@@ -599,7 +600,7 @@ __global__ void __launch_bounds__(256) batch_kernel(BatchLaunch B) {
 #ifndef MRG_GANG_LOCK
 #define MRG_GANG_LOCK 3
 #endif
-constexpr int kGangLock = MRG_GANG_LOCK;  // barriers per unrolled main-loop iteration (1 or 3)
+constexpr int kGangLock = MRG_GANG_LOCK;  // barriers per unrolled main-loop iteration (0, 1 or 3)
 
 template <int KIND>
 __device__ __forceinline__ void gang_tile(const GenLaunch& L, uint32_t sblk, uint32_t chunk) {
@@ -672,11 +673,13 @@ __global__ void __launch_bounds__(512) batch_gang_kernel(BatchLaunch B) {
         }
         // the barriers of the gang's longer main loops (kGangLock per
         // unrolled iteration, as run_chunk passes them)
-        for (uint32_t i = nit; i < nbar; ++i) {
-            __builtin_amdgcn_s_barrier();
-            if constexpr (kGangLock == 3) {
+        if constexpr (kGangLock != 0) {
+            for (uint32_t i = nit; i < nbar; ++i) {
                 __builtin_amdgcn_s_barrier();
-                __builtin_amdgcn_s_barrier();
+                if constexpr (kGangLock == 3) {
+                    __builtin_amdgcn_s_barrier();
+                    __builtin_amdgcn_s_barrier();
+                }
             }
         }
         if (wave == 0) {
@@ -909,22 +912,36 @@ hipError_t launch_advance(int gen, uint32_t* streams, uint64_t n, uint64_t steps
 // Chunks hold at least 96 units (32 with one stream per lane on grids below
 // two waves per SIMD); at most 65535 chunks.  A narrower store is used when n_streams or the output
 // alignment does not allow the wide one.
+// Index of the tuned shape for a call: kind (dist, dtype) and size class of
+// its draw count.
+static const TunedShape& tuned_shape(const GenLaunch& L) {
+    int kind;
+    switch (L.dist) {
+        case kUniform: kind = L.dtype == kF64 ? 0 : 1; break;
+        case kRaw: kind = 2; break;
+        case kNormal: kind = L.dtype == kF64 ? 3 : 4; break;
+        default: kind = L.dtype == kF64 ? 5 : 6; break;
+    }
+    const uint64_t n = L.q * L.S + L.r;
+    const int cls = n < (1ull << 18) ? 0 : n < (1ull << 22) ? 1 : n < (1ull << 26) ? 2 : n < (1ull << 29) ? 3 : 4;
+    return kTuned[kind][cls];
+}
+
 void plan_generate(GenLaunch& L) {
     const int esz = L.dtype == kF64 ? 8 : 4;
-    const bool plain = L.dist == kUniform || L.dist == kRaw;
+    const TunedShape& t = tuned_shape(L);
     const bool cfg_given = L.block || L.chunk || L.spl || (L.arith && L.arith != kArith31);
     if (!L.arith) L.arith = kArithF64;
     const bool spl_auto = !L.spl;
-    if (!L.spl) L.spl = plain ? 16 / esz : 2;
-    const bool block_auto = !L.block;
-    if (block_auto) L.block = plain ? 512 : 256;
+    if (spl_auto) L.spl = t.spl;
+    if (!L.block) L.block = t.block;
     if (!cfg_given) {
         // Non-temporal stores when rows start on 128-byte lines; otherwise
         // the line a wave shares with its neighbour is written in two halves,
         // which L2 merges only when it keeps them (2^30 fp64 uniforms over
         // 262,143 streams: 2.13 ms with nt stores, 1.80 ms without)
         L.nontemporal = (static_cast<uint64_t>(L.S) * esz) % 128 == 0;
-        L.xcd = !(plain && esz == 4);
+        L.xcd = t.xcd;
     }
     // at most 16 bytes per store; narrower when the shape does not allow it
     while (L.spl * esz > 16) L.spl /= 2;
@@ -933,29 +950,15 @@ void plan_generate(GenLaunch& L) {
         while (L.spl > 1 && 64ull * L.spl > L.S) L.spl /= 2;
     const uint64_t cnt_max = L.q + (L.r ? 1 : 0);
     const uint64_t units_max = L.dist == kNormal ? (cnt_max + 1) / 2 : cnt_max;
-    const uint64_t target_waves = L.dist == kNormal ? 8192 : (L.dist == kExponential ? 4096 : (esz == 8 ? 2048 : 4096));
-    // chunk for about target_waves waves, at least min_units units each
-    auto auto_chunk = [&](uint64_t n_sblk, uint64_t min_units) {
-        uint64_t w = (target_waves + n_sblk - 1) / n_sblk;
-        const uint64_t w_cap = (units_max + min_units - 1) / min_units;
+    const uint64_t n_sblk = (static_cast<uint64_t>(L.S) + 64ull * L.spl - 1) / (64ull * L.spl);
+    if (!L.chunk) {
+        // chunk for about t.waves waves, at least t.min_units units each
+        uint64_t w = (t.waves + n_sblk - 1) / n_sblk;
+        const uint64_t w_cap = (units_max + t.min_units - 1) / t.min_units;
         if (w > w_cap) w = w_cap;
         if (w < 1) w = 1;
         const uint64_t c = (units_max + w - 1) / w;
-        return static_cast<uint32_t>(c > 0xffffffffull ? 0xffffffffull : (c ? c : 1));
-    };
-    uint64_t n_sblk = (static_cast<uint64_t>(L.S) + 64ull * L.spl - 1) / (64ull * L.spl);
-    if (!L.chunk) {
-        L.chunk = auto_chunk(n_sblk, 96);
-        const uint64_t waves = n_sblk * (units_max ? (units_max + L.chunk - 1) / L.chunk : 0);
-        if (!cfg_given && waves < 2048) {
-            // A grid below two waves per SIMD is launch-latency-bound: more,
-            // shorter waves finish sooner (1,024 streams x 1,024 fp64
-            // uniforms: 36 us at two streams per lane and 96-draw chunks,
-            // 25 us at one stream per lane and 32-64-draw chunks)
-            L.spl = 1;
-            n_sblk = (static_cast<uint64_t>(L.S) + 63) / 64;
-            L.chunk = auto_chunk(n_sblk, 32);
-        }
+        L.chunk = static_cast<uint32_t>(c > 0xffffffffull ? 0xffffffffull : (c ? c : 1));
     }
     uint64_t nch = units_max ? (units_max + L.chunk - 1) / L.chunk : 0;
     if (nch > 65535) {
@@ -964,15 +967,10 @@ void plan_generate(GenLaunch& L) {
         nch = (units_max + c - 1) / c;
     }
     L.n_chunks = static_cast<uint32_t>(nch);
-    if (!cfg_given && plain && esz == 8) {
-        // fp64 uniforms are store-bound: once the grid fills the chip (two
-        // waves per SIMD), eight waves per block (one block per CU at the
-        // default size) writing each row together beat free-running waves;
-        // smaller grids are launch-latency-bound and run free in 256-thread
-        // blocks, which start sooner
-        L.lock = n_sblk * nch >= 2048;
-        if (!L.lock && block_auto) L.block = 256;
-    }
+    // Lockstep rows (store-bound fp64 uniforms): once the grid fills the
+    // chip (two waves per SIMD), the waves of a block writing each row
+    // together beat free-running waves; smaller grids are launch-latency-bound
+    if (!cfg_given && t.lock) L.lock = n_sblk * nch >= 2048;
     const uint64_t wpb = static_cast<uint64_t>(L.block) / 64;
     const uint64_t gx = (n_sblk + wpb - 1) / wpb;
     if (L.xcd && (gx * nch) % 8) L.xcd = 0;  // the remap needs a multiple of 8 blocks

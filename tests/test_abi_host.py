@@ -514,3 +514,21 @@ def test_batch_gang_plans():
     for g in (3, 5, 16):
         st, _ = _plan_status(reqs, (512, 0, 0, g))
         assert st == -1
+
+
+def test_tuned_table_resolution_matches_the_library():
+    """The tuner works out the launch shape each candidate table entry gives
+    (tune_plain.resolve); for the committed table that must be the shape the
+    library's automatic plan reports, at every kind's representative sizes
+    and at a few others of each size class."""
+    from paper_2201_06604_amd import tune_plain as T
+    table = T.read_table()
+    others = [(100, 7), (3, 1000001), (131071, 33), (1 << 20, 64), (65, 100000), (4096, 1 << 16), (77, 5000)]
+    for k, (name, dist, dtype) in enumerate(T.KINDS):
+        for S, per in T.CLASSES + others:
+            for extra in (0, 3):
+                n = S * per + extra
+                c = 0 if n < 1 << 18 else 1 if n < 1 << 22 else 2 if n < 1 << 26 else 3 if n < 1 << 29 else 4
+                want = T.resolve(table[k][c], S, n, dist, dtype)
+                got = P.mrg_generate_plan(S, n, dist, dtype)
+                assert got == want, (name, S, n, got, want)
