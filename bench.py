@@ -184,19 +184,21 @@ def trace_summary(kt_csv, bench_log):
 
 def valu_summary(valu_csv, bench_log):
     """Lane-instructions per unit of the measured kernels from a rocprofv3
-    --pmc SQ_INSTS_VALU run of bench.py (wave-instructions per dispatch x 64
-    lanes / the units the dispatch processed), written to the JSON the bench
-    reads while the kernel sources are unchanged.  Units: draws for the
-    2^30-draw generate launches (the dispatch of each kind with the most
-    instructions) and for the last batch launch (a graph replay over the
-    whole mix); tables for the 10^6-table launch."""
+    --pmc run of bench.py with SQ_INSTS_VALU and GRBM_GUI_ACTIVE (wave-
+    instructions per dispatch x 64 lanes / the units the dispatch processed),
+    and each kernel's VALU busy (SQ_INSTS_VALU x 4 cycles over the 1,024 SIMDs
+    and the dispatch's busy cycles per XCD, GRBM_GUI_ACTIVE / 8), written to
+    the JSON the bench reads while the kernel sources are unchanged.  Units:
+    draws for the 2^30-draw generate launches (the dispatch of each kind with
+    the most instructions) and for the last batch launch (a graph replay over
+    the whole mix); tables for the 10^6-table launch; replicates for the
+    largest Fisher launch (Table 2, B = 10,027,008)."""
     import csv
     per = {}
     for r in csv.DictReader(open(valu_csv)):
-        if r["Counter_Name"] != "SQ_INSTS_VALU":
-            continue
         key = (int(r["Dispatch_Id"]), r["Kernel_Name"])
-        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        c = per.setdefault(key, {})
+        c[r["Counter_Name"]] = c.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
     line = None
     with open(bench_log) as f:
         for ln in f:
@@ -206,24 +208,37 @@ def valu_summary(valu_csv, bench_log):
         sys.exit("no JSON line in " + bench_log)
 
     def biggest(pred):
-        ks = [(v, k) for k, v in per.items() if pred(k[1])]
-        return max(ks)[0] if ks else None
+        ks = [(c.get("SQ_INSTS_VALU", 0.0), d, k) for (d, k), c in per.items() if pred(k)]
+        if not ks:
+            return None
+        _, d, k = max(ks)
+        return per[(d, k)]
 
-    out = {"source_sha256": line["roofline"]["source_sha256"], "per_unit": {}, "workload": {}}
+    def busy(c):
+        cyc = c.get("GRBM_GUI_ACTIVE", 0.0) / 8
+        return round(c["SQ_INSTS_VALU"] * 4 / (1024 * cyc), 4) if cyc else None
+
+    out = {"source_sha256": line["roofline"]["source_sha256"], "per_unit": {}, "valu_busy": {}, "workload": {}}
+
+    def put(name, c, units, what):
+        if c is None:
+            return
+        out["per_unit"][name] = c["SQ_INSTS_VALU"] * 64 / units
+        out["valu_busy"][name] = busy(c)
+        out["workload"][name] = what
+
     for name, prefix in [("f64_uniform", "gen_kernel<0, 0,"), ("f32_uniform", "gen_kernel<0, 1,"),
-                         ("f64_normal", "gen_kernel<1, 0,"), ("f64_exponential", "gen_kernel<2, 0,")]:
-        v = biggest(lambda k, p=prefix: p in k)
-        if v is not None:
-            out["per_unit"][name] = v * 64 / N
-            out["workload"][name] = f"{S_STREAMS} streams x {PER_STREAM} draws, per draw"
-    v = biggest(lambda k: "tables_kernel" in k)
-    if v is not None:
-        out["per_unit"]["tables_kernel"] = v * 64 / 1_000_000
-        out["workload"]["tables_kernel"] = "10^6 tables of the CFG4 mix, per table"
-    batch = sorted((d, v) for (d, k), v in per.items() if "batch_kernel" in k)
+                         ("f64_normal", "gen_kernel<1, 0,"), ("f64_exponential", "gen_kernel<2, 0,"),
+                         ("f32_normal", "gen_kernel<1, 1,"), ("f32_exponential", "gen_kernel<2, 1,")]:
+        put(name, biggest(lambda k, p=prefix: p in k), N, f"{S_STREAMS} streams x {PER_STREAM} draws, per draw")
+    put("tables_kernel", biggest(lambda k: "tables_kernel" in k), 1_000_000,
+        "10^6 tables of the CFG4 mix, per table")
+    put("fisher_kernel", biggest(lambda k: "fisher_kernel" in k), 10027008,
+        "Table 2 (7 x 12), B = 10,027,008 replicates, per replicate")
+    batch = sorted((d, k) for (d, k) in per if "batch_kernel" in k or "batch_gang_kernel" in k)
     if batch and "batched" in line:
-        out["per_unit"]["batch_kernel"] = batch[-1][1] * 64 / line["batched"]["draws"]
-        out["workload"]["batch_kernel"] = "the 4,096-request mix (last launch), per draw"
+        put("batch_kernel", per[batch[-1]], line["batched"]["draws"],
+            "the 4,096-request mix (last launch: a graph replay), per draw")
     with open(VALU_JSON, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
@@ -437,9 +452,17 @@ def bench_batched(torch, P, workloads, reps=3, with_oracle=True):
     kind = {(0, 0): "f64_uniform", (0, 1): "f32_uniform", (1, 0): "f64_normal", (1, 1): "f32_normal",
             (2, 0): "f64_exponential", (2, 1): "f32_exponential"}
     ops = sum(r["n"] * OPS_PER_DRAW[kind[(r["dist"], r["dtype"])]] for r in reqs)
-    res["roofline"] = alu_roofline(ops / total_n, total_n, best_ms)
+    vp = valu_profile()
+    meas = vp["per_unit"].get("batch_kernel") if vp else None
+    res["roofline"] = alu_roofline(ops / total_n, total_n, best_ms, meas)
     res["roofline"]["hbm_frac"] = round(out_bytes / (best_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
-    res["roofline"]["kernel"] = "batch_kernel (persistent, graph-replayed)"
+    res["roofline"]["kernel"] = ("batch_gang_kernel" if best.get("gang_waves", 1) > 1 else "batch_kernel") + \
+        " (persistent, graph-replayed)"
+    if meas is not None:
+        # issued lane-instructions (algorithmic work plus idle lanes of partial
+        # waves, per-tile jumps and tails) against the same ceiling
+        res["roofline"]["issued_frac"] = round(meas * total_n / (best_ms * 1e-3) / VALU_PEAK_LANE_INSTR, 4)
+        res["roofline"]["valu_busy_profiled"] = vp.get("valu_busy", {}).get("batch_kernel")
     res["speedup_makespan"] = round(res["plain"]["makespan_ms"] / res["batched"]["makespan_ms"], 2)
     res["p99_ratio_plain_over_batched"] = round(res["plain"]["p99_ms"] / res["batched"]["p99_ms"], 2)
     for m in meta:
@@ -508,7 +531,10 @@ def bench_tables(torch, P, workloads, reps=10, with_oracle=True):
     if vp and "tables_kernel" in vp.get("per_unit", {}):
         res["roofline"] = alu_roofline(vp["per_unit"]["tables_kernel"], n, ms)
         res["roofline"]["kernel"] = "tables_kernel"
-        res["roofline"]["note"] = "ops_per_unit = measured VALU lane-instructions per table (data-dependent loops)"
+        res["roofline"]["valu_busy_profiled"] = vp.get("valu_busy", {}).get("tables_kernel")
+        res["roofline"]["note"] = ("ops_per_unit = issued VALU lane-slots per table (wave-instructions x 64, "
+                                   "SQ_INSTS_VALU): the inversion loops' trip counts depend on the margins, and "
+                                   "a wave issues until its longest lane is done")
     del d, tabs, stats
     if with_oracle:
         res["oracle"] = tables_oracle_sample(I, J, rows, cols, workloads.random_seed())
@@ -524,10 +550,15 @@ def bench_tables(torch, P, workloads, reps=10, with_oracle=True):
         b.record()
         torch.cuda.synchronize()
         ms = a.elapsed_time(b)
-        fis[name.split("_")[1].split(".")[0]] = {
+        key = name.split("_")[1].split(".")[0]
+        fis[key] = {
             "table": f"{tab.shape[0]}x{tab.shape[1]}", "B": B, "ms": round(ms, 2),
             "Mtables_per_s": round(B / ms / 1e3, 2), "pvalue": round(P.mrg_fisher_pvalue(int(cnt.item()), B), 6),
             "paper_V100_s": paper_s}
+        if key == "week" and vp and "fisher_kernel" in vp.get("per_unit", {}):
+            fis[key]["roofline"] = alu_roofline(vp["per_unit"]["fisher_kernel"], B, ms)
+            fis[key]["roofline"]["kernel"] = "fisher_kernel"
+            fis[key]["roofline"]["valu_busy_profiled"] = vp.get("valu_busy", {}).get("fisher_kernel")
         del d
     res["fisher"] = fis
     if with_oracle:
@@ -751,7 +782,9 @@ def main():
         out32 = torch.empty(N, dtype=torch.float32, device=dev)
         for name, dist, dt, o, esz in [("f32_uniform", P.MRG_UNIFORM, P.MRG_F32, out32, 4),
                                        ("f64_normal", P.MRG_NORMAL, P.MRG_F64, out, 8),
-                                       ("f64_exponential", P.MRG_EXPONENTIAL, P.MRG_F64, out, 8)]:
+                                       ("f64_exponential", P.MRG_EXPONENTIAL, P.MRG_F64, out, 8),
+                                       ("f32_normal", P.MRG_NORMAL, P.MRG_F32, out32, 4),
+                                       ("f32_exponential", P.MRG_EXPONENTIAL, P.MRG_F32, out32, 4)]:
             ms = timed_median(torch, lambda: P.mrg_generate(streams, N, dist, dt, 1.0, out=o))
             gbps = N * esz / (ms * 1e-3) / 1e9
             var[name] = {"GSamples_per_s": round(N / (ms * 1e-3) / 1e9, 2),
@@ -764,7 +797,8 @@ def main():
         if not args.no_cpu:
             import oracle as O
             for name, od, odt in [("f32_uniform", O.UNIFORM, O.F32), ("f64_normal", O.NORMAL, O.F64),
-                                  ("f64_exponential", O.EXPONENTIAL, O.F64)]:
+                                  ("f64_exponential", O.EXPONENTIAL, O.F64), ("f32_normal", O.NORMAL, O.F32),
+                                  ("f32_exponential", O.EXPONENTIAL, O.F32)]:
                 rate, dt_s, th = oracle_rate(seed, 16384, PER_STREAM, od, odt)
                 var[name]["oracle"] = {"value": round(rate, 4), "unit": "GSamples/s", "cores": th,
                                        "kind": "oracle",

@@ -203,10 +203,13 @@ mrg_status build(mrg_batch_plan& P) {
         L.param = q.dist == MRG_EXPONENTIAL ? 1.0 / q.param : 1.0;
         const int esz = static_cast<int>(esz_of(q.dtype));
         const bool plain = q.dist == MRG_UNIFORM || q.dist == MRG_RAW;
-        int spl = (plain && P.wide != 1) ? 16 / esz : 1;
+        // uniform/raw tiles store up to 16 bytes per lane (4-byte outputs: 1 or
+        // 4 streams per lane), transform tiles run two streams per lane (two
+        // independent chains) where the request allows
+        int spl = P.wide == 1 ? 1 : (plain ? 16 / esz : 2);
         while (spl > 1 && (q.n_streams % spl || reinterpret_cast<uintptr_t>(q.out) % (spl * esz))) spl /= 2;
         while (spl > 1 && 64ull * spl > q.n_streams) spl /= 2;  // a wave's streams must exist
-        if (esz == 4 && spl == 2) spl = 1;  // tiles of 4-byte outputs use 1 or 4 streams per lane
+        if (plain && esz == 4 && spl == 2) spl = 1;
         if (P.wide == 0) {
             // a wave covers 64 * spl streams and issues its instructions for
             // all of them: keep the narrowest width that leaves the fewest
@@ -218,7 +221,7 @@ mrg_status build(mrg_batch_plan& P) {
             };
             int best = spl;
             for (int v = spl / 2; v >= 1; v /= 2)
-                if (!(esz == 4 && v == 2) && slots(v) < slots(best)) best = v;
+                if (!(plain && esz == 4 && v == 2) && slots(v) < slots(best)) best = v;
             spl = best;
         }
         L.spl = spl;

@@ -39,7 +39,8 @@ void plan_generate(GenLaunch& L);
 // Kinds of tile the persistent kernel can run (dist, dtype, streams per lane).
 enum BatchKind {
     kBUniF64x1, kBUniF64x2, kBUniF32x1, kBUniF32x4, kBRawU32x1, kBRawU32x4,
-    kBNormF64, kBNormF32, kBExpF64, kBExpF32, kBKinds
+    kBNormF64, kBNormF32, kBExpF64, kBExpF32,
+    kBNormF64x2, kBNormF32x2, kBExpF64x2, kBExpF32x2, kBKinds
 };
 
 struct BatchReq {       // one request, static for a plan
@@ -63,8 +64,8 @@ struct BatchSlot {      // per-request counters, reset by every launch
 enum BatchClass { kClsNormal = 0, kClsExp = 1, kClsPlain = 2, kClasses = 3 };
 
 inline int batch_kind_class(int kind) {
-    if (kind == kBNormF64 || kind == kBNormF32) return kClsNormal;
-    if (kind == kBExpF64 || kind == kBExpF32) return kClsExp;
+    if (kind == kBNormF64 || kind == kBNormF32 || kind == kBNormF64x2 || kind == kBNormF32x2) return kClsNormal;
+    if (kind == kBExpF64 || kind == kBExpF32 || kind == kBExpF64x2 || kind == kBExpF32x2) return kClsExp;
     return kClsPlain;
 }
 

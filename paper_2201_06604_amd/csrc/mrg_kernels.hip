@@ -470,6 +470,10 @@ __device__ __forceinline__ void batch_tile(const GenLaunch& L, uint32_t sblk, ui
     if constexpr (KIND == kBNormF32) run_chunk<kNormal, kF32, kArithF64, 1, false>(L, sblk, chunk);
     if constexpr (KIND == kBExpF64) run_chunk<kExponential, kF64, kArithF64, 1, false>(L, sblk, chunk);
     if constexpr (KIND == kBExpF32) run_chunk<kExponential, kF32, kArithF64, 1, false>(L, sblk, chunk);
+    if constexpr (KIND == kBNormF64x2) run_chunk<kNormal, kF64, kArithF64, 2, false>(L, sblk, chunk);
+    if constexpr (KIND == kBNormF32x2) run_chunk<kNormal, kF32, kArithF64, 2, false>(L, sblk, chunk);
+    if constexpr (KIND == kBExpF64x2) run_chunk<kExponential, kF64, kArithF64, 2, false>(L, sblk, chunk);
+    if constexpr (KIND == kBExpF32x2) run_chunk<kExponential, kF32, kArithF64, 2, false>(L, sblk, chunk);
 }
 
 // A wave has stored its tile of request `req`: count the tile off the request;
@@ -534,11 +538,19 @@ __device__ __forceinline__ void batch_worker(const BatchLaunch& B, uint32_t firs
         const uint32_t kind = __builtin_amdgcn_readfirstlane(B.reqs[req].kind);
         const GenLaunch& L = B.reqs[req].L;
         if constexpr (CLS == kClsNormal) {
-            if (kind == kBNormF64) batch_tile<kBNormF64>(L, sblk, chunk);
-            else batch_tile<kBNormF32>(L, sblk, chunk);
+            switch (kind) {
+                case kBNormF64: batch_tile<kBNormF64>(L, sblk, chunk); break;
+                case kBNormF32: batch_tile<kBNormF32>(L, sblk, chunk); break;
+                case kBNormF64x2: batch_tile<kBNormF64x2>(L, sblk, chunk); break;
+                default: batch_tile<kBNormF32x2>(L, sblk, chunk); break;
+            }
         } else if constexpr (CLS == kClsExp) {
-            if (kind == kBExpF64) batch_tile<kBExpF64>(L, sblk, chunk);
-            else batch_tile<kBExpF32>(L, sblk, chunk);
+            switch (kind) {
+                case kBExpF64: batch_tile<kBExpF64>(L, sblk, chunk); break;
+                case kBExpF32: batch_tile<kBExpF32>(L, sblk, chunk); break;
+                case kBExpF64x2: batch_tile<kBExpF64x2>(L, sblk, chunk); break;
+                default: batch_tile<kBExpF32x2>(L, sblk, chunk); break;
+            }
         } else {
             switch (kind) {
                 case kBUniF64x1: batch_tile<kBUniF64x1>(L, sblk, chunk); break;
@@ -614,6 +626,10 @@ __device__ __forceinline__ void gang_tile(const GenLaunch& L, uint32_t sblk, uin
     if constexpr (KIND == kBNormF32) run_chunk<kNormal, kF32, kArithF64, 1, false, kGangLock>(L, sblk, chunk);
     if constexpr (KIND == kBExpF64) run_chunk<kExponential, kF64, kArithF64, 1, false, kGangLock>(L, sblk, chunk);
     if constexpr (KIND == kBExpF32) run_chunk<kExponential, kF32, kArithF64, 1, false, kGangLock>(L, sblk, chunk);
+    if constexpr (KIND == kBNormF64x2) run_chunk<kNormal, kF64, kArithF64, 2, false, kGangLock>(L, sblk, chunk);
+    if constexpr (KIND == kBNormF32x2) run_chunk<kNormal, kF32, kArithF64, 2, false, kGangLock>(L, sblk, chunk);
+    if constexpr (KIND == kBExpF64x2) run_chunk<kExponential, kF64, kArithF64, 2, false, kGangLock>(L, sblk, chunk);
+    if constexpr (KIND == kBExpF32x2) run_chunk<kExponential, kF32, kArithF64, 2, false, kGangLock>(L, sblk, chunk);
 }
 
 // Main-loop iterations of a wave tile: run_chunk passes kGangLock barriers
@@ -667,7 +683,11 @@ __global__ void __launch_bounds__(512) batch_gang_kernel(BatchLaunch B) {
                 case kBNormF64: gang_tile<kBNormF64>(L, sblk, chunk); break;
                 case kBNormF32: gang_tile<kBNormF32>(L, sblk, chunk); break;
                 case kBExpF64: gang_tile<kBExpF64>(L, sblk, chunk); break;
-                default: gang_tile<kBExpF32>(L, sblk, chunk); break;
+                case kBExpF32: gang_tile<kBExpF32>(L, sblk, chunk); break;
+                case kBNormF64x2: gang_tile<kBNormF64x2>(L, sblk, chunk); break;
+                case kBNormF32x2: gang_tile<kBNormF32x2>(L, sblk, chunk); break;
+                case kBExpF64x2: gang_tile<kBExpF64x2>(L, sblk, chunk); break;
+                default: gang_tile<kBExpF32x2>(L, sblk, chunk); break;
             }
             finish_tile(B, req, one);
         }
@@ -1117,8 +1137,12 @@ int batch_kind(int dist, int dtype, int spl) {
             if (dtype == kF64) return spl == 2 ? kBUniF64x2 : kBUniF64x1;
             return spl == 4 ? kBUniF32x4 : kBUniF32x1;
         case kRaw: return spl == 4 ? kBRawU32x4 : kBRawU32x1;
-        case kNormal: return dtype == kF64 ? kBNormF64 : kBNormF32;
-        default: return dtype == kF64 ? kBExpF64 : kBExpF32;
+        case kNormal:
+            if (spl == 2) return dtype == kF64 ? kBNormF64x2 : kBNormF32x2;
+            return dtype == kF64 ? kBNormF64 : kBNormF32;
+        default:
+            if (spl == 2) return dtype == kF64 ? kBExpF64x2 : kBExpF32x2;
+            return dtype == kF64 ? kBExpF64 : kBExpF32;
     }
 }
 

@@ -48,6 +48,11 @@ MIX = [
     (1100, 1100 * 23 + 77, P.MRG_UNIFORM, P.MRG_F64, 1.0),
     (1031, 1031 * 11 + 3, P.MRG_UNIFORM, P.MRG_F32, 1.0),
     (520, 520 * 40, P.MRG_RAW, P.MRG_U32, 1.0),
+    # transforms over even stream counts of at least 128: two streams per lane
+    (130, 130 * 21 + 5, P.MRG_NORMAL, P.MRG_F64, 1.0),
+    (256, 256 * 9 + 3, P.MRG_EXPONENTIAL, P.MRG_F32, 1.5),
+    (200, 200 * 40 + 1, P.MRG_NORMAL, P.MRG_F32, 1.0),
+    (1024, 1024 * 7, P.MRG_EXPONENTIAL, P.MRG_F64, 1.0),
 ]
 
 
