@@ -17,6 +17,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "mrg_logtab.h"
 #include "mrg_math.h"
 
 namespace mrg355 {
@@ -277,7 +278,7 @@ __device__ __forceinline__ double sqrt_radius(double x) {
 // three steps' constants, and scaling by a power of two commutes with
 // rounding, so log_unit<SCALE>(u) is bit for bit SCALE * log_unit(u).
 template <int SCALE = 1>
-__device__ __forceinline__ double log_unit(double u) {
+__device__ __forceinline__ double log_unit_series(double u) {
     static_assert(SCALE == 1 || SCALE == -1 || SCALE == 2 || SCALE == -2, "power-of-two scale");
     int k = __builtin_amdgcn_frexp_exp(u);          // u = mant * 2^k, mant in [1/2, 1)
     double m = __builtin_amdgcn_frexp_mant(u);
@@ -310,6 +311,66 @@ __device__ __forceinline__ double log_unit(double u) {
     constexpr double kLn2Hi = 6.93147180369123816490e-01;  // ln 2 to 32 bits: k * hi exact for |k| < 2^20
     constexpr double kLn2Lo = 1.90821492927058770002e-10;  // ln 2 - hi
     return __builtin_fma(kd, kLn2Hi * SCALE, __builtin_fma(kd, kLn2Lo * SCALE, log_m));
+}
+
+// The table of log_unit (mrg_logtab.h) in LDS: every kernel whose code calls
+// log_unit stages it once per block with stage_log_table() (all threads, then
+// a barrier) before any call.
+static __constant__ LogTable g_logtab = kLogTable;
+
+__device__ __forceinline__ double* log_table_lds() {
+    __shared__ double tab[kLogTabN * 3];
+    return tab;
+}
+
+// Every wave writes the whole table (the same values): a loop of fixed trip
+// count over the wave's lanes, with no dependence on the block size (a loop
+// bounded by threadIdx and blockDim made the compiler treat later row addresses
+// as divergent).
+__device__ __forceinline__ void stage_log_table() {
+    double* t = log_table_lds();
+    const int lane = static_cast<int>(threadIdx.x & 63);
+#pragma unroll
+    for (int k = 0; k < kLogTabN * 3 / 64; ++k) {
+        const int i = lane + 64 * k;
+        t[i] = g_logtab.e[i / 3][i % 3];
+    }
+    __syncthreads();
+}
+
+// log(u) for the generators' uniforms, u in [2^-33, 1), by table: u = m 2^k
+// with m in [1/2, 1); the top 7 fraction bits of m pick an interval of width
+// 1/256 whose entry holds R, a multiple of 2^-7 near 1/m (R = 1 on the last
+// interval), and -log(R) = hi + lo.  t = m R - 1 is exact (|t| <= 2^-7, a
+// multiple of 2^-60), log(m) = -log(R) + log1p(t) with log1p(t) = t + t^2 P(t)
+// through t^8 (the next term is below 2^-56 of t), and k ln2 + hi is exact
+// (hi a multiple of 2^-40, ln2_hi of 2^-32, |k| <= 33).  Near u = 1 (k = 0,
+// R = 1) the result is log1p(t) alone, accurate relative to its own size.
+// SCALE (1, -1, 2 or -2) multiplies the result exactly.
+// mrg_transform_accuracy compares it with the HIP library's log over any
+// range of generator outputs.
+template <int SCALE = 1>
+__device__ __forceinline__ double log_unit(double u) {
+    static_assert(SCALE == 1 || SCALE == -1 || SCALE == 2 || SCALE == -2, "power-of-two scale");
+    const int k = __builtin_amdgcn_frexp_exp(u);
+    const double m = __builtin_amdgcn_frexp_mant(u);  // [1/2, 1)
+    const uint32_t j = (static_cast<uint32_t>(__double2hiint(m)) >> 13) & (kLogTabN - 1);
+    const double* e = log_table_lds() + 3 * j;
+    const double t = __builtin_fma(m, e[0], -1.0);
+    double p = -1.0 / 8.0;
+    p = __builtin_fma(p, t, 1.0 / 7.0);
+    p = __builtin_fma(p, t, -1.0 / 6.0);
+    p = __builtin_fma(p, t, 1.0 / 5.0);
+    p = __builtin_fma(p, t, -1.0 / 4.0);
+    p = __builtin_fma(p, t, 1.0 / 3.0);
+    p = __builtin_fma(p, t, -1.0 / 2.0);
+    const double q = (t * t) * p;
+    const double kd = static_cast<double>(k);
+    constexpr double kLn2Hi = 6.93147180369123816490e-01;  // ln 2 to 32 bits: k * hi exact
+    constexpr double kLn2Lo = 1.90821492927058770002e-10;  // ln 2 - hi
+    const double a = __builtin_fma(kd, kLn2Hi, e[1]);
+    const double lo = __builtin_fma(kd, kLn2Lo, e[2]);
+    return (a + (t + (q + lo))) * SCALE;
 }
 
 // ----------------------------------------------- transforms for fp32 output

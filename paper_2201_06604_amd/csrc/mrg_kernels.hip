@@ -380,6 +380,7 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
 // ending their wave (a wave's lane 0 always holds a stream).
 template <int DIST, int DTYPE, int ARITH, int SPL, bool NT, bool LOCK>
 __global__ void __launch_bounds__(1024) gen_kernel(GenLaunch L) {
+    if constexpr ((DIST == kNormal || DIST == kExponential) && DTYPE == kF64) stage_log_table();
     // Block -> (stream block, chunk).  With xcd remapping, consecutive logical
     // blocks (neighbouring row segments) land on one XCD, whose L2 then sees
     // contiguous runs of every row; blocks are dealt to the 8 XCDs in turn.
@@ -579,6 +580,7 @@ __device__ __forceinline__ uint32_t home_rank(const BatchLaunch& B, int cls) {
 // then helps the other classes until every queue is empty.  The three loops
 // run one after another, so their register live ranges never overlap.
 __global__ void __launch_bounds__(256) batch_kernel(BatchLaunch B) {
+    stage_log_table();
     constexpr uint32_t kNone = 0xffffffffu;
     if (blockIdx.x == 0 && threadIdx.x < 64) B.head->t_start = __builtin_amdgcn_s_memrealtime();
     if (blockIdx.x < B.block_lo[1]) {
@@ -653,6 +655,7 @@ __device__ __forceinline__ uint32_t tile_iters(const BatchLaunch& B, const Batch
 // that no wave can overwrite it before every wave has read it.  All control
 // flow around the barriers is block-uniform.
 __global__ void __launch_bounds__(512) batch_gang_kernel(BatchLaunch B) {
+    stage_log_table();
     __shared__ uint32_t next_gang;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t one = lane == 0 ? 1u : 0u;
@@ -1225,6 +1228,7 @@ __device__ __forceinline__ uint64_t paper_stream_of(int dist, uint32_t g0, uint3
 
 template <int DIST, int DTYPE, int G>
 __global__ void __launch_bounds__(256) paper_kernel(PaperLaunch L) {
+    if constexpr ((DIST == kNormal || DIST == kExponential) && DTYPE == kF64) stage_log_table();
     using Engine = typename EngineOf<G>::T;
     using T = typename ElemOf<DTYPE>::T;
     const uint64_t id = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;

@@ -152,7 +152,7 @@ def test_lockstep_blocks(cfg, dist, dtype, S, n):
     run_case(rec, n, dist, dtype, 1.0, cfg)
 
 
-@pytest.mark.parametrize("S,n", [(100003, 100003 * 130 + 77), (100000, 100000 * 500 + 99999), (65536, 65536 * 300)])
+@pytest.mark.parametrize("S,n", [(100003, 100003 * 700 + 77), (100000, 100000 * 700 + 99999), (65536, 65536 * 1100)])
 def test_default_plan_lockstep_at_scale(S, n):
     """Automatic launches large enough for lockstep blocks: ragged stream
     counts (the last block's spare waves only pass the barriers), odd S (one

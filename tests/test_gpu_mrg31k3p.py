@@ -139,7 +139,7 @@ def test_launch_shapes(cfg):
     run(rec, 300 * 11 + 5, P.MRG_NORMAL, P.MRG_F64, cfg=cfg)
 
 
-@pytest.mark.parametrize("S,n", [(65536, 65536 * 300), (100003, 100003 * 130 + 77)])
+@pytest.mark.parametrize("S,n", [(65536, 65536 * 1100), (100003, 100003 * 700 + 77)])
 def test_default_plan_lockstep_at_scale(S, n):
     """fp64 uniforms at sizes where the automatic plan runs lockstep blocks
     (several chunks per stream; an odd stream count with spare waves)."""
