@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "mrg_logtab.h"
+#include "mrg_sincostab.h"
 #include "mrg_math.h"
 
 namespace mrg355 {
@@ -205,7 +206,7 @@ struct F64Engine {
 // r^16: the next terms are below 2^-58 at |r| = 1/4); the quadrant n mod 4
 // swaps and negates.  mrg_transform_accuracy compares both results with the
 // HIP library's sincospi over any range of generator outputs.
-__device__ __forceinline__ void sincospi_unit(double t, double* sp, double* cp) {
+__device__ __forceinline__ void sincospi_unit_series(double t, double* sp, double* cp) {
     const double n = __builtin_rint(t + t);
     const double r = __builtin_fma(n, -0.5, t);
     const double z = r * r;
@@ -313,29 +314,74 @@ __device__ __forceinline__ double log_unit_series(double u) {
     return __builtin_fma(kd, kLn2Hi * SCALE, __builtin_fma(kd, kLn2Lo * SCALE, log_m));
 }
 
-// The table of log_unit (mrg_logtab.h) in LDS: every kernel whose code calls
-// log_unit stages it once per block with stage_log_table() (all threads, then
-// a barrier) before any call.
+// The tables of log_unit (mrg_logtab.h) and sincospi_unit (mrg_sincostab.h)
+// in LDS: every kernel whose code evaluates the fp64 transforms stages them
+// once per block with stage_tables() (all threads, then a barrier) before any
+// call.
 static __constant__ LogTable g_logtab = kLogTable;
+static __constant__ SinCosTable g_sincostab = kSinCosTable;
 
 __device__ __forceinline__ double* log_table_lds() {
     __shared__ double tab[kLogTabN * 3];
     return tab;
 }
 
-// Every wave writes the whole table (the same values): a loop of fixed trip
+__device__ __forceinline__ double* sincos_table_lds() {
+    __shared__ double tab[kSinCosTabN * 4];
+    return tab;
+}
+
+// Every wave writes both tables whole (the same values): loops of fixed trip
 // count over the wave's lanes, with no dependence on the block size (a loop
 // bounded by threadIdx and blockDim made the compiler treat later row addresses
 // as divergent).
-__device__ __forceinline__ void stage_log_table() {
+__device__ __forceinline__ void stage_tables() {
     double* t = log_table_lds();
+    double* c = sincos_table_lds();
     const int lane = static_cast<int>(threadIdx.x & 63);
 #pragma unroll
     for (int k = 0; k < kLogTabN * 3 / 64; ++k) {
         const int i = lane + 64 * k;
         t[i] = g_logtab.e[i / 3][i % 3];
     }
+#pragma unroll
+    for (int k = 0; k < (kSinCosTabN * 4 + 63) / 64; ++k) {
+        const int i = lane + 64 * k;
+        if (i < kSinCosTabN * 4) c[i] = g_sincostab.e[i / 4][i % 4];
+    }
     __syncthreads();
+}
+
+// sin(pi t) and cos(pi t) for t = 2u in (0, 2) (the Box-Muller angle), by
+// table: j = rint(64 t) and d = t - j/64 (exact: t and j/64 are within a
+// factor of two, or j = 0; |d| <= 1/128); with s_j = sin(pi j/64) and
+// c_j = cos(pi j/64) from the table as hi + lo,
+// sin(pi t) = s_j + (s_j (cos(pi d) - 1) + c_j sin(pi d))
+// and cos(pi t) = c_j + (c_j (cos(pi d) - 1) - s_j sin(pi d)), where
+// sin(pi d) runs through d^7 and cos(pi d) - 1 through d^8 (the next terms
+// are below 2^-60 of their sums at |d| = 1/128).  On the axes (j a multiple
+// of 32) the table holds exact zeros and ones, so results near the zeros of
+// sin and cos keep their relative accuracy.  mrg_transform_accuracy compares
+// both results with the HIP library's sincospi over any range of generator
+// outputs.
+__device__ __forceinline__ void sincospi_unit(double t, double* sp, double* cp) {
+    const double jd = __builtin_rint(t * 64.0);
+    const double d = __builtin_fma(jd, -1.0 / 64.0, t);
+    const double* e = sincos_table_lds() + 4 * static_cast<int>(jd);
+    const double z = d * d;
+    double ps = -0.5992645293207921;  // -pi^7/7!
+    ps = __builtin_fma(ps, z, 2.5501640398773455);  // pi^5/5!
+    ps = __builtin_fma(ps, z, -5.16771278004997);   // -pi^3/3!
+    ps = __builtin_fma(ps, z, 3.141592653589793);   // pi
+    const double sd = d * ps;
+    double pc = 0.2353306303588932;                 // pi^8/8!
+    pc = __builtin_fma(pc, z, -1.3352627688545895); // -pi^6/6!
+    pc = __builtin_fma(pc, z, 4.0587121264167685);  // pi^4/4!
+    pc = __builtin_fma(pc, z, -4.934802200544679);  // -pi^2/2!
+    const double cm1 = z * pc;
+    const double sh = e[0], sl = e[1], ch = e[2], cl = e[3];
+    *sp = sh + __builtin_fma(sh, cm1, __builtin_fma(ch, sd, sl));
+    *cp = ch + __builtin_fma(ch, cm1, __builtin_fma(-sh, sd, cl));
 }
 
 // log(u) for the generators' uniforms, u in [2^-33, 1), by table: u = m 2^k

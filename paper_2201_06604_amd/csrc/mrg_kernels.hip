@@ -39,6 +39,7 @@ static constexpr JumpTables kHostTab = make_jump_tables<kGen32k3a>();
 static constexpr JumpTables kHostTab31 = make_jump_tables<kGen31k3p>();
 __constant__ StreamDigits g_dig = make_stream_digits<kGen32k3a>(kHostTab);
 __constant__ StreamDigits g_dig31 = make_stream_digits<kGen31k3p>(kHostTab31);
+__constant__ StepDigitsF64 g_stepdig = make_step_digits_f64<kGen32k3a>(kHostTab);
 
 // ------------------------------------------------------------------ jumps
 template <int G>
@@ -70,6 +71,26 @@ template <int G>
 __device__ __forceinline__ void dev_jump(uint32_t x[6], uint64_t e) {
     for (int b = 0; e; ++b, e >>= 1)
         if (e & 1) dev_apply<G>(dev_tab<G>().step_pow2[0][b], dev_tab<G>().step_pow2[1][b], x);
+}
+
+// x <- A^e x for MRG32k3a by base-64 digits of e (wave-uniform): one exact
+// fp64 matrix-vector product per nonzero digit instead of one integer product
+// per set bit.  x canonical in and out.
+__device__ __forceinline__ void dev_jump_digits(uint32_t x[6], uint64_t e) {
+    double v1[3] = {static_cast<double>(x[0]), static_cast<double>(x[1]), static_cast<double>(x[2])};
+    double v2[3] = {static_cast<double>(x[3]), static_cast<double>(x[4]), static_cast<double>(x[5])};
+    for (int d = 0; e; ++d, e >>= 6) {
+        const uint32_t v = static_cast<uint32_t>(e & 63);
+        if (v) {
+            matvec_f64(g_stepdig.m[d][0][v], v1, kM1d, kInvM1);
+            matvec_f64(g_stepdig.m[d][1][v], v2, kM2d, kInvM2);
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+        x[w] = static_cast<uint32_t>(v1[w]);
+        x[3 + w] = static_cast<uint32_t>(v2[w]);
+    }
 }
 
 // Largest float <= u (u in [2^-126, 1)) from v = u 2^-896, a normal double
@@ -238,7 +259,10 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
 #pragma unroll
         for (int w = 0; w < 6; ++w) x[w] = rec[w];
         const uint64_t jump = L.offset + u0 * kSpu;
-        if (jump) dev_jump<G>(x, jump);
+        if (jump) {
+            if constexpr (ARITH == kArithF64) dev_jump_digits(x, jump);
+            else dev_jump<G>(x, jump);
+        }
         e[i].load(x);
     }
 
@@ -380,7 +404,7 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
 // ending their wave (a wave's lane 0 always holds a stream).
 template <int DIST, int DTYPE, int ARITH, int SPL, bool NT, bool LOCK>
 __global__ void __launch_bounds__(1024) gen_kernel(GenLaunch L) {
-    if constexpr ((DIST == kNormal || DIST == kExponential) && DTYPE == kF64) stage_log_table();
+    if constexpr ((DIST == kNormal || DIST == kExponential) && DTYPE == kF64) stage_tables();
     // Block -> (stream block, chunk).  With xcd remapping, consecutive logical
     // blocks (neighbouring row segments) land on one XCD, whose L2 then sees
     // contiguous runs of every row; blocks are dealt to the 8 XCDs in turn.
@@ -580,7 +604,7 @@ __device__ __forceinline__ uint32_t home_rank(const BatchLaunch& B, int cls) {
 // then helps the other classes until every queue is empty.  The three loops
 // run one after another, so their register live ranges never overlap.
 __global__ void __launch_bounds__(256) batch_kernel(BatchLaunch B) {
-    stage_log_table();
+    stage_tables();
     constexpr uint32_t kNone = 0xffffffffu;
     if (blockIdx.x == 0 && threadIdx.x < 64) B.head->t_start = __builtin_amdgcn_s_memrealtime();
     if (blockIdx.x < B.block_lo[1]) {
@@ -655,7 +679,7 @@ __device__ __forceinline__ uint32_t tile_iters(const BatchLaunch& B, const Batch
 // that no wave can overwrite it before every wave has read it.  All control
 // flow around the barriers is block-uniform.
 __global__ void __launch_bounds__(512) batch_gang_kernel(BatchLaunch B) {
-    stage_log_table();
+    stage_tables();
     __shared__ uint32_t next_gang;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t one = lane == 0 ? 1u : 0u;
@@ -1228,7 +1252,7 @@ __device__ __forceinline__ uint64_t paper_stream_of(int dist, uint32_t g0, uint3
 
 template <int DIST, int DTYPE, int G>
 __global__ void __launch_bounds__(256) paper_kernel(PaperLaunch L) {
-    if constexpr ((DIST == kNormal || DIST == kExponential) && DTYPE == kF64) stage_log_table();
+    if constexpr ((DIST == kNormal || DIST == kExponential) && DTYPE == kF64) stage_tables();
     using Engine = typename EngineOf<G>::T;
     using T = typename ElemOf<DTYPE>::T;
     const uint64_t id = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;

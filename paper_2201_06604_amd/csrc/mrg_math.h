@@ -253,4 +253,32 @@ MRG_HD constexpr StreamDigits make_stream_digits(const JumpTables& T) {
     return D;
 }
 
+// Step jumps by base-64 digits, for the fp64 engine: digit[d][j][v] =
+// A_j^(v 64^d) with entries as doubles, so A^e for any e < 2^64 is the product
+// of at most eleven entries, one per nonzero base-64 digit of e, each applied
+// with matvec_f64 (a chunk start inside a stream: e = offset + j * chunk).
+constexpr int kStepDigits = 11;
+struct StepDigitsF64 {
+    double m[kStepDigits][2][64][9];
+};
+
+template <int G>
+MRG_HD constexpr StepDigitsF64 make_step_digits_f64(const JumpTables& T) {
+    constexpr int B = G == kGen32k3a ? 32 : 31;
+    StepDigitsF64 D{};
+    for (int j = 0; j < 2; ++j) {
+        const uint32_t c = G == kGen32k3a ? comp_c(j) : comp_c31(j);
+        for (int d = 0; d < kStepDigits; ++d) {
+            const int bit = 6 * d;
+            const Mat3 base = bit < 64 ? T.step_pow2[j][bit] : identity();  // A^(64^d)
+            Mat3 P = identity();
+            for (int v = 0; v < 64; ++v) {
+                for (int k = 0; k < 9; ++k) D.m[d][j][v][k] = static_cast<double>(P.a[k]);
+                P = matmul<B>(P, base, c);
+            }
+        }
+    }
+    return D;
+}
+
 }  // namespace mrg355

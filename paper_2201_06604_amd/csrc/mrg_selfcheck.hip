@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(64) accuracy_clear_kernel(unsigned long long* 
 // among equal ones, the largest z.
 template <int G>
 __global__ void __launch_bounds__(256) accuracy_kernel(int fn, uint64_t z0, uint64_t z1, unsigned long long* res) {
-    stage_log_table();
+    stage_tables();
     __shared__ unsigned long long bins[kAccuracyBins];
     __shared__ unsigned long long worst;
     if (threadIdx.x < kAccuracyBins) bins[threadIdx.x] = 0;
