@@ -247,7 +247,8 @@ def valu_summary(valu_csv, bench_log):
         "10^6 tables of the CFG4 mix, per table")
     put("fisher_kernel", biggest(lambda k: "fisher_kernel" in k), 10027008,
         "Table 2 (7 x 12), B = 10,027,008 replicates, per replicate")
-    batch = sorted((d, k) for (d, k) in per if "batch_kernel" in k or "batch_gang_kernel" in k)
+    batch = sorted((d, k) for (d, k) in per
+                   if any(n + "(" in k for n in ("batch_kernel", "batch_gang_kernel", "batch_gang_narrow_kernel")))
     if batch and "batched" in line:
         put("batch_kernel", per[batch[-1]], line["batched"]["draws"],
             "the 4,096-request mix (last launch: a graph replay), per draw")
@@ -469,7 +470,9 @@ def bench_batched(torch, P, workloads, reps=3, with_oracle=True):
     meas = vp["per_unit"].get("batch_kernel") if vp else None
     res["roofline"] = alu_roofline(ops / total_n, total_n, best_ms, meas)
     res["roofline"]["hbm_frac"] = round(out_bytes / (best_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
-    res["roofline"]["kernel"] = ("batch_gang_kernel" if best.get("gang_waves", 1) > 1 else "batch_kernel") + \
+    res["roofline"]["kernel"] = ("batch_kernel" if best.get("gang_waves", 1) <= 1 else
+                                 "batch_gang_narrow_kernel" if best.get("wide_stores") == 1 else
+                                 "batch_gang_kernel") + \
         " (persistent, graph-replayed)"
     if meas is not None:
         # issued_frac counts the algorithmic work plus idle lanes of partial

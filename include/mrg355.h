@@ -349,9 +349,13 @@ typedef struct {
  *   tile_units      most draws (normal: pairs) one wave makes in one tile
  *   waves_per_simd  waves per SIMD of the persistent grid (1..16), capped at
  *                   what the kernel's registers allow to be resident at once
- *   wide_stores     0 = automatic (stores up to 16 bytes wide where a
- *                   request allows, unless a narrower width leaves fewer
- *                   lanes idle), 1 = force one stream per lane
+ *   wide_stores     1 = one stream per lane; 2 = stores up to 16 bytes
+ *                   wide (several streams per lane) where a request allows,
+ *                   unless a narrower width leaves fewer lanes idle;
+ *                   0 = automatic: 1 in gang mode, 2 otherwise.  In gang
+ *                   mode a plan of one-stream tiles runs a kernel holding
+ *                   only their code, which fits up to six waves per SIMD
+ *                   (the kernel with every width fits three)
  *   gang_waves      1 = every wave takes tiles on its own, from one queue per
  *                   class (normal, exponential, uniform/raw); 2, 4 or 8 = a
  *                   block of that many waves takes a gang of that many tiles
@@ -413,9 +417,10 @@ mrg_status mrg_batch_launch_static(const mrg_batch_plan* plan, hipStream_t strea
 mrg_status mrg_batch_request_times(const mrg_batch_plan* plan, const void* dev_workspace,
                                    uint64_t* host_ticks, hipStream_t stream);
 
-/* Autotuner: time candidate shapes (tile_units in {512, ..., 8192} x
- * gang_waves in {1, 4, 8} x wide_stores in {0, 1} x waves_per_simd in
- * {2, 3, 4}) of the plan on the GPU with its own requests,
+/* Autotuner: time candidate shapes (tile_units in {256, ..., 8192} x
+ * gang_waves in {1, 4, 8} x wide_stores in {1, 2} x waves_per_simd in
+ * {2, 3, 4, 6}; a waves setting that the kernel's registers cap to the grid of
+ * the one before is skipped) of the plan on the GPU with its own requests,
  * in `dev_workspace` (capacity `workspace_bytes`; shapes whose workspace would
  * not fit are skipped: mrg_batch_autotune_workspace_size gives the capacity
  * that fits every candidate), keep

@@ -37,6 +37,7 @@ struct mrg_batch_plan {
     uint32_t tile_lo[kClasses + 1];
     double cls_cost[kClasses];
     uint32_t n_gangs;  // gang mode: tiles holds n_gangs * gang entries (padding: req = kNoRequest)
+    uint32_t narrow;   // every request runs one stream per lane (the narrow gang kernel serves it)
     std::vector<uint32_t> fin_req;
     std::vector<uint64_t> fin_pre;
     uint64_t fin_total;
@@ -46,9 +47,12 @@ struct mrg_batch_plan {
 
 namespace {
 
-constexpr uint32_t kDefaultTileUnits = 4096;
-constexpr uint32_t kDefaultWavesPerSimd = 8;
-constexpr uint32_t kDefaultGang = 1;
+// The shape the autotuner picks for the 4,096-request mix of lengths 10^3 to
+// 10^7 and 64 to 1,024 streams: gangs of 8 waves, one stream per lane (the
+// narrow kernel), 256-unit tiles, 4 waves per SIMD.
+constexpr uint32_t kDefaultTileUnits = 256;
+constexpr uint32_t kDefaultWavesPerSimd = 4;
+constexpr uint32_t kDefaultGang = 8;
 constexpr unsigned kBatchBlock = 256;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -187,6 +191,10 @@ mrg_status build(mrg_batch_plan& P) {
     P.fin_pre.assign(1, 0);
     std::vector<double> cost;
     std::vector<uint64_t> len;  // draw units of each tile
+    // store width: automatic is one stream per lane in gang mode, where a
+    // plan of such tiles runs the kernel that holds their code alone (more
+    // waves fit), and the widest fitting width otherwise
+    const uint32_t wide = P.wide ? P.wide : (P.gang > 1 ? 1u : 2u);
     for (size_t i = 0; i < P.user.size(); ++i) {
         const mrg_request& q = P.user[i].q;
         BatchReq R{};
@@ -206,11 +214,11 @@ mrg_status build(mrg_batch_plan& P) {
         // uniform/raw tiles store up to 16 bytes per lane (4-byte outputs: 1 or
         // 4 streams per lane), transform tiles run two streams per lane (two
         // independent chains) where the request allows
-        int spl = P.wide == 1 ? 1 : (plain ? 16 / esz : 2);
+        int spl = wide == 1 ? 1 : (plain ? 16 / esz : 2);
         while (spl > 1 && (q.n_streams % spl || reinterpret_cast<uintptr_t>(q.out) % (spl * esz))) spl /= 2;
         while (spl > 1 && 64ull * spl > q.n_streams) spl /= 2;  // a wave's streams must exist
         if (plain && esz == 4 && spl == 2) spl = 1;
-        if (P.wide == 0) {
+        if (wide == 2) {
             // a wave covers 64 * spl streams and issues its instructions for
             // all of them: keep the narrowest width that leaves the fewest
             // lanes idle in the request's last stream block (S = 300: one
@@ -287,6 +295,8 @@ mrg_status build(mrg_batch_plan& P) {
     P.tiles.swap(sorted);
     }
     P.fin_total = P.fin_pre.back();
+    P.narrow = 1;
+    for (const BatchReq& R : P.reqs) P.narrow &= batch_kind_narrow(static_cast<int>(R.kind)) ? 1u : 0u;
     // workspace layout
     const size_t n_req = P.reqs.size();
     P.off_slots = 256;
@@ -313,6 +323,7 @@ BatchLaunch launch_args(const mrg_batch_plan& P, void* ws) {
     B.n_fin = static_cast<uint32_t>(P.fin_req.size());
     B.fin_total = P.fin_total;
     B.n_gangs = P.n_gangs;
+    B.narrow = P.narrow;
     for (int c = 0; c <= kClasses; ++c) B.tile_lo[c] = P.tile_lo[c];
     return B;
 }
@@ -325,6 +336,16 @@ mrg_status upload(const mrg_batch_plan& P, void* ws, hipStream_t stream) {
     return MRG_OK;
 }
 
+// Blocks per CU of the persistent grid: those of the requested waves per SIMD
+// (4 SIMDs per CU), capped at what the kernel's registers allow at once.
+uint64_t blocks_per_cu(const mrg_batch_plan& P) {
+    if (P.n_gangs)
+        return std::min<uint64_t>(static_cast<uint64_t>(batch_gang_blocks_per_cu(64 * P.gang, P.narrow != 0)),
+                                  std::max<uint64_t>(1, 4 * P.waves_per_simd / P.gang));
+    return std::min<uint64_t>(static_cast<uint64_t>(batch_blocks_per_cu()),
+                              std::max<uint64_t>(1, 4 * P.waves_per_simd / (kBatchBlock / 64)));
+}
+
 mrg_status launch(const mrg_batch_plan& P, void* ws, hipStream_t stream, BatchSlot* host_slots = nullptr) {
     if (P.tiles.empty() && P.reqs.empty()) return MRG_OK;
     BatchLaunch B = launch_args(P, ws);
@@ -333,8 +354,7 @@ mrg_status launch(const mrg_batch_plan& P, void* ws, hipStream_t stream, BatchSl
         // one queue of gangs; the grid is what is resident at once at the
         // requested waves per SIMD, and no larger than the gang count
         const unsigned block = 64 * P.gang;
-        const uint64_t per_cu = std::min<uint64_t>(static_cast<uint64_t>(batch_gang_blocks_per_cu(block)),
-                                                   std::max<uint64_t>(1, 4 * P.waves_per_simd / P.gang));
+        const uint64_t per_cu = blocks_per_cu(P);
         const uint64_t grid = std::min<uint64_t>(static_cast<uint64_t>(device_cu_count()) * per_cu, P.n_gangs);
         hipError_t e = launch_batch(B, static_cast<unsigned>(grid), block, stream);
         if (e != hipSuccess) return mrg355_fail(MRG_E_HIP, "batch launch: %s", hipGetErrorString(e));
@@ -345,8 +365,7 @@ mrg_status launch(const mrg_batch_plan& P, void* ws, hipStream_t stream, BatchSl
     // least one block and at most one per 4 of its tiles); blocks move on to
     // the other classes when their own queue is empty.
     const uint64_t wpb = kBatchBlock / 64;
-    const uint64_t per_cu = std::min<uint64_t>(static_cast<uint64_t>(batch_blocks_per_cu()),
-                                               std::max<uint64_t>(1, 4 * P.waves_per_simd / wpb));
+    const uint64_t per_cu = blocks_per_cu(P);
     const uint64_t total = std::max<uint64_t>(kClasses, static_cast<uint64_t>(device_cu_count()) * per_cu);
     double tot_cost = 0.0;
     for (int c = 0; c < kClasses; ++c) tot_cost += P.cls_cost[c];
@@ -445,7 +464,7 @@ mrg_status mrg_batch_plan_create(mrg_generator gen, const mrg_request* reqs, siz
     if (n_req && !reqs) return mrg355_fail(MRG_E_INVALID_ARG, "reqs is NULL");
     if (n_req > 0xfffffffful) return mrg355_fail(MRG_E_INVALID_ARG, "too many requests");
     if (cfg && cfg->waves_per_simd > 16) return mrg355_fail(MRG_E_INVALID_ARG, "waves_per_simd above 16");
-    if (cfg && cfg->wide_stores > 1) return mrg355_fail(MRG_E_INVALID_ARG, "wide_stores must be 0 or 1");
+    if (cfg && cfg->wide_stores > 2) return mrg355_fail(MRG_E_INVALID_ARG, "wide_stores must be 0, 1 or 2");
     if (cfg && cfg->gang_waves && cfg->gang_waves != 1 && cfg->gang_waves != 2 && cfg->gang_waves != 4 &&
         cfg->gang_waves != 8)
         return mrg355_fail(MRG_E_INVALID_ARG, "gang_waves must be 0, 1, 2, 4 or 8");
@@ -491,10 +510,10 @@ mrg_status mrg_batch_workspace_size(const mrg_batch_plan* plan, size_t* bytes) {
 // lane (widest stores a request allows, or one stream per lane) x waves per
 // SIMD.  Tile length sets the per-stream work-item count (a stream of u units
 // is cut into ceil(u / tile_units) work-items).
-static constexpr uint32_t kTuneTileUnits[] = {512, 1024, 2048, 4096, 8192};
+static constexpr uint32_t kTuneTileUnits[] = {256, 512, 1024, 2048, 4096, 8192};
 static constexpr uint32_t kTuneGang[] = {1, 4, 8};
-static constexpr uint32_t kTuneWide[] = {0, 1};
-static constexpr uint32_t kTuneWaves[] = {2, 3, 4};
+static constexpr uint32_t kTuneWide[] = {1, 2};
+static constexpr uint32_t kTuneWaves[] = {2, 3, 4, 6};
 
 mrg_status mrg_batch_autotune_workspace_size(const mrg_batch_plan* plan, size_t* bytes) {
     if (!plan || !bytes) return mrg355_fail(MRG_E_INVALID_ARG, "NULL plan or bytes");
@@ -603,8 +622,14 @@ mrg_status mrg_batch_autotune(mrg_batch_plan* plan, void* dev_workspace, size_t 
                 if ((st = build(*plan))) break;
                 if (plan->bytes > workspace_bytes) continue;  // does not fit the caller's workspace
                 if ((st = upload(*plan, dev_workspace, stream))) break;
+                uint64_t timed_per_cu = 0;
                 for (uint32_t w : kTuneWaves) {
                     plan->waves_per_simd = w;
+                    // a waves setting the kernel's registers cap to the
+                    // grid of the previous one is not timed again
+                    const uint64_t per_cu = blocks_per_cu(*plan);
+                    if (per_cu == timed_per_cu) continue;
+                    timed_per_cu = per_cu;
                     if ((st = launch(*plan, dev_workspace, stream))) break;  // warm-up
                     e = hipEventRecord(a, stream);
                     for (int rep = 0; rep < 3 && !st; ++rep) st = launch(*plan, dev_workspace, stream);

@@ -89,10 +89,15 @@ struct BatchLaunch {    // kernel arguments
     uint64_t fin_total;
     uint32_t n_gangs;                 // gang mode: tiles[g*wpb .. g*wpb+wpb-1] is gang g; 0 = class queues
     uint32_t grid;                    // blocks of the persistent kernel
+    uint32_t narrow;                  // gang mode: 1 = every tile is of one stream per lane
 };
 
 hipError_t launch_batch(const BatchLaunch& B, unsigned grid, unsigned block, hipStream_t s);
-int batch_gang_blocks_per_cu(unsigned block);
+int batch_gang_blocks_per_cu(unsigned block, bool narrow);
+inline bool batch_kind_narrow(int kind) {
+    return kind == kBUniF64x1 || kind == kBUniF32x1 || kind == kBRawU32x1 || kind == kBNormF64 || kind == kBNormF32 ||
+           kind == kBExpF64 || kind == kBExpF32;
+}
 
 }  // namespace mrg355
 

@@ -678,7 +678,12 @@ __device__ __forceinline__ uint32_t tile_iters(const BatchLaunch& B, const Batch
 // atomic, increment 1 on lane 0 only), and two barriers bracket the read so
 // that no wave can overwrite it before every wave has read it.  All control
 // flow around the barriers is block-uniform.
-__global__ void __launch_bounds__(512) batch_gang_kernel(BatchLaunch B) {
+//
+// NARROW: the plan holds only tiles of one stream per lane.  Their code alone
+// fits the registers of six resident waves per SIMD, where the code of every
+// kind together allows three.
+template <bool NARROW>
+__device__ __forceinline__ void gang_loop(const BatchLaunch& B) {
     stage_tables();
     __shared__ uint32_t next_gang;
     const uint32_t lane = threadIdx.x & 63;
@@ -700,21 +705,33 @@ __global__ void __launch_bounds__(512) batch_gang_kernel(BatchLaunch B) {
             const uint32_t chunk = __builtin_amdgcn_readfirstlane(gt[wave].chunk);
             const uint32_t kind = __builtin_amdgcn_readfirstlane(B.reqs[req].kind);
             const GenLaunch& L = B.reqs[req].L;
-            switch (kind) {
-                case kBUniF64x1: gang_tile<kBUniF64x1>(L, sblk, chunk); break;
-                case kBUniF64x2: gang_tile<kBUniF64x2>(L, sblk, chunk); break;
-                case kBUniF32x1: gang_tile<kBUniF32x1>(L, sblk, chunk); break;
-                case kBUniF32x4: gang_tile<kBUniF32x4>(L, sblk, chunk); break;
-                case kBRawU32x1: gang_tile<kBRawU32x1>(L, sblk, chunk); break;
-                case kBRawU32x4: gang_tile<kBRawU32x4>(L, sblk, chunk); break;
-                case kBNormF64: gang_tile<kBNormF64>(L, sblk, chunk); break;
-                case kBNormF32: gang_tile<kBNormF32>(L, sblk, chunk); break;
-                case kBExpF64: gang_tile<kBExpF64>(L, sblk, chunk); break;
-                case kBExpF32: gang_tile<kBExpF32>(L, sblk, chunk); break;
-                case kBNormF64x2: gang_tile<kBNormF64x2>(L, sblk, chunk); break;
-                case kBNormF32x2: gang_tile<kBNormF32x2>(L, sblk, chunk); break;
-                case kBExpF64x2: gang_tile<kBExpF64x2>(L, sblk, chunk); break;
-                default: gang_tile<kBExpF32x2>(L, sblk, chunk); break;
+            if constexpr (NARROW) {
+                switch (kind) {
+                    case kBUniF64x1: gang_tile<kBUniF64x1>(L, sblk, chunk); break;
+                    case kBUniF32x1: gang_tile<kBUniF32x1>(L, sblk, chunk); break;
+                    case kBRawU32x1: gang_tile<kBRawU32x1>(L, sblk, chunk); break;
+                    case kBNormF64: gang_tile<kBNormF64>(L, sblk, chunk); break;
+                    case kBNormF32: gang_tile<kBNormF32>(L, sblk, chunk); break;
+                    case kBExpF64: gang_tile<kBExpF64>(L, sblk, chunk); break;
+                    default: gang_tile<kBExpF32>(L, sblk, chunk); break;
+                }
+            } else {
+                switch (kind) {
+                    case kBUniF64x1: gang_tile<kBUniF64x1>(L, sblk, chunk); break;
+                    case kBUniF64x2: gang_tile<kBUniF64x2>(L, sblk, chunk); break;
+                    case kBUniF32x1: gang_tile<kBUniF32x1>(L, sblk, chunk); break;
+                    case kBUniF32x4: gang_tile<kBUniF32x4>(L, sblk, chunk); break;
+                    case kBRawU32x1: gang_tile<kBRawU32x1>(L, sblk, chunk); break;
+                    case kBRawU32x4: gang_tile<kBRawU32x4>(L, sblk, chunk); break;
+                    case kBNormF64: gang_tile<kBNormF64>(L, sblk, chunk); break;
+                    case kBNormF32: gang_tile<kBNormF32>(L, sblk, chunk); break;
+                    case kBExpF64: gang_tile<kBExpF64>(L, sblk, chunk); break;
+                    case kBExpF32: gang_tile<kBExpF32>(L, sblk, chunk); break;
+                    case kBNormF64x2: gang_tile<kBNormF64x2>(L, sblk, chunk); break;
+                    case kBNormF32x2: gang_tile<kBNormF32x2>(L, sblk, chunk); break;
+                    case kBExpF64x2: gang_tile<kBExpF64x2>(L, sblk, chunk); break;
+                    default: gang_tile<kBExpF32x2>(L, sblk, chunk); break;
+                }
             }
             finish_tile(B, req, one);
         }
@@ -737,6 +754,13 @@ __global__ void __launch_bounds__(512) batch_gang_kernel(BatchLaunch B) {
         g = next_gang;
         __syncthreads();
     }
+}
+
+__global__ void __launch_bounds__(512) batch_gang_kernel(BatchLaunch B) { gang_loop<false>(B); }
+
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6)))
+batch_gang_narrow_kernel(BatchLaunch B) {
+    gang_loop<true>(B);
 }
 
 // States of requests split over several chunks: cur <- A^(steps consumed) cur,
@@ -1142,20 +1166,22 @@ hipError_t launch_store_ceiling(const GenLaunch& L, hipStream_t s) {
     return launch_ceiling_t<float, 1>(L, 0.5f, s);
 }
 
-int batch_gang_blocks_per_cu(unsigned block) {
+int batch_gang_blocks_per_cu(unsigned block, bool narrow) {
     static std::mutex mu;
-    static int cached[9] = {0};  // by waves per block
+    static int cached[2][9] = {};  // by kernel and waves per block
     const unsigned w = block / 64;
     if (w == 0 || w > 8) return 1;
     std::lock_guard<std::mutex> lk(mu);
-    if (!cached[w]) {
+    int& c = cached[narrow ? 1 : 0][w];
+    if (!c) {
+        const void* k = narrow ? reinterpret_cast<const void*>(batch_gang_narrow_kernel)
+                               : reinterpret_cast<const void*>(batch_gang_kernel);
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(batch_gang_kernel),
-                                                         static_cast<int>(block), 0) != hipSuccess || n <= 0)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, static_cast<int>(block), 0) != hipSuccess || n <= 0)
             n = 1;
-        cached[w] = n;
+        c = n;
     }
-    return cached[w];
+    return c;
 }
 
 int batch_kind(int dist, int dtype, int spl) {
@@ -1201,7 +1227,8 @@ hipError_t launch_batch(const BatchLaunch& B_in, unsigned grid, unsigned block, 
     hipLaunchKernelGGL(batch_init_kernel, dim3(grid1d(B.n_req ? B.n_req : 1, 256)), dim3(256), 0, s, B);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (B.n_gangs) hipLaunchKernelGGL(batch_gang_kernel, dim3(grid), dim3(block), 0, s, B);
+    if (B.n_gangs && B.narrow) hipLaunchKernelGGL(batch_gang_narrow_kernel, dim3(grid), dim3(block), 0, s, B);
+    else if (B.n_gangs) hipLaunchKernelGGL(batch_gang_kernel, dim3(grid), dim3(block), 0, s, B);
     else hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), 0, s, B);
     e = hipGetLastError();
     if (e != hipSuccess || B.fin_total == 0) return e;

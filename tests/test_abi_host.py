@@ -238,13 +238,15 @@ def test_batch_plan_validation():
     sz, nt = ctypes.c_size_t(), ctypes.c_size_t()
     assert P.lib().mrg_batch_workspace_size(plan, ctypes.byref(sz)) == 0 and sz.value % 256 == 0
     assert P.lib().mrg_batch_tile_count(plan, ctypes.byref(nt)) == 0
-    assert nt.value == 2  # 64 streams x 10 draws each: one wave-tile per request (2 streams/lane)
+    # 64 streams x 10 draws each: one wave tile per request (one stream per
+    # lane, the automatic width in gang mode), in one gang of 8 waves
+    assert nt.value == 8
     most = ctypes.c_size_t()
     assert P.lib().mrg_batch_autotune_workspace_size(plan, ctypes.byref(most)) == 0
     assert most.value >= sz.value and most.value % 256 == 0
     P.lib().mrg_batch_plan_destroy(plan)
-    # a long request: smaller trial tiles need a larger workspace than the default cut
-    st, plan = _plan_status([_req(base, 1024, 1024 * 200000, out=1 << 32)])
+    # a long request: smaller trial tiles need a larger workspace than a 4096-unit cut
+    st, plan = _plan_status([_req(base, 1024, 1024 * 200000, out=1 << 32)], (4096, 0, 0, 1))
     assert st == 0
     assert P.lib().mrg_batch_workspace_size(plan, ctypes.byref(sz)) == 0
     assert P.lib().mrg_batch_autotune_workspace_size(plan, ctypes.byref(most)) == 0
@@ -264,6 +266,8 @@ def test_batch_plan_validation():
         assert st == -1, reqs
     st, _ = _plan_status(ok, (0, 17, 0))
     assert st == -1  # waves_per_simd above 16
+    st, _ = _plan_status(ok, (0, 0, 3))
+    assert st == -1  # wide_stores above 2
     arr = (P.mrg_request * 1)(*ok[:1])
     plan = ctypes.c_void_p()
     assert P.lib().mrg_batch_plan_create(2, arr, 1, None, ctypes.byref(plan)) == -3
@@ -281,18 +285,20 @@ def test_batch_tiles_cover_requests():
     reqs = [_req(base, S1, n1, out=1 << 32),
             _req(base + S1 * 72, S2, n2, dist=1, out=(1 << 33)),
             _req(base + (S1 + S2) * 72, S3, n3, out=(1 << 34))]
-    st, plan = _plan_status(reqs, (100, 0, 0))
-    assert st == 0
     nt = ctypes.c_size_t()
-    P.lib().mrg_batch_tile_count(plan, ctypes.byref(nt))
-    want = 3 * ((1001 + 99) // 100) + 2 * ((151 + 99) // 100) + 2 * ((250 + 99) // 100)
-    assert nt.value == want
-    P.lib().mrg_batch_plan_destroy(plan)
-    st, plan = _plan_status(reqs, (100, 0, 1))  # one stream per lane everywhere
-    assert st == 0
-    P.lib().mrg_batch_tile_count(plan, ctypes.byref(nt))
-    assert nt.value == 3 * 11 + 2 * 2 + 4 * 3
-    P.lib().mrg_batch_plan_destroy(plan)
+    want = 3 * ((1001 + 99) // 100) + 2 * ((151 + 99) // 100) + 2 * ((250 + 99) // 100)   # 43
+    narrow = 3 * 11 + 2 * 2 + 4 * 3                                                       # 49
+    # (tile_units, waves, wide_stores, gang): automatic width outside gang mode
+    # is the widest fitting one; in gang mode it is one stream per lane.  Gang
+    # plans pad each class (here uniform and normal) to whole gangs.
+    cases = {(100, 0, 0, 1): want, (100, 0, 2, 1): want, (100, 0, 1, 1): narrow,
+             (100, 0, 2, 4): 40 + 4, (100, 0, 0, 8): 48 + 8, (100, 0, 1, 8): 48 + 8}
+    for cfg, n in cases.items():
+        st, plan = _plan_status(reqs, cfg)
+        assert st == 0
+        P.lib().mrg_batch_tile_count(plan, ctypes.byref(nt))
+        assert nt.value == n, (cfg, nt.value)
+        P.lib().mrg_batch_plan_destroy(plan)
 
 
 # ------------------------------------------------------------------ serving

@@ -132,7 +132,11 @@ def test_batch_equals_plain_equals_oracle():
                                  dict(gang_waves=8, tile_units=333, waves_per_simd=2),
                                  dict(gang_waves=4, tile_units=1, waves_per_simd=1),
                                  dict(gang_waves=8, tile_units=64, wide_stores=1),
-                                 dict(gang_waves=2, tile_units=100000, waves_per_simd=16)],
+                                 dict(gang_waves=2, tile_units=100000, waves_per_simd=16),
+                                 dict(gang_waves=4, wide_stores=1, waves_per_simd=6),
+                                 dict(gang_waves=8, wide_stores=1, tile_units=7, waves_per_simd=3),
+                                 dict(gang_waves=4, wide_stores=2), dict(gang_waves=8, wide_stores=2, tile_units=64),
+                                 dict(wide_stores=2, tile_units=300)],
                          ids=str)
 def test_batch_shape_invariance(cfg):
     A, B = Mix(MIX, 1), Mix(MIX, 1)
@@ -164,12 +168,13 @@ def test_batch_relaunch_continues_streams():
         assert torch.equal(A.streams[i], B.streams[i])
 
 
-@pytest.mark.parametrize("gang", [1, 4])
-def test_batch_graph_replay_matches_eager(gang):
+@pytest.mark.parametrize("cfg", [dict(tile_units=200, gang_waves=1), dict(tile_units=200, gang_waves=4),
+                                 dict(tile_units=200, gang_waves=4, wide_stores=2, waves_per_simd=6)], ids=str)
+def test_batch_graph_replay_matches_eager(cfg):
     """Capture one launch in a HIP graph, replay it three times with eager
     work in between; each replay must equal the matching eager launch."""
     A, B = Mix(MIX, 3), Mix(MIX, 3)
-    planA = P.BatchPlan(A.requests(), dict(tile_units=200, gang_waves=gang))
+    planA = P.BatchPlan(A.requests(), cfg)
     planA.upload()
     planB = P.BatchPlan(B.requests(), dict(tile_units=200))
     planB.upload()
@@ -200,13 +205,13 @@ def test_batch_autotune_leaves_streams_and_stays_exact():
     small = P.BatchPlan(A.requests(), dict(tile_units=512))
     plan = P.BatchPlan(A.requests())
     assert plan.autotune_workspace_size() >= small.workspace_size()
-    plan.alloc_workspace()  # the default cut's size: autotune grows it for the smaller trial tiles
+    plan.alloc_workspace()  # the default cut's size: autotune grows it where a trial cut needs more
     plan.upload()
     before = [t.clone() for t in A.streams]
     best, ms = plan.autotune()
     assert plan.workspace_size() <= plan._ws_bytes
-    assert best["tile_units"] in (512, 1024, 2048, 4096, 8192) and best["waves_per_simd"] in (2, 3, 4)
-    assert best["gang_waves"] in (1, 4, 8) and best["wide_stores"] in (0, 1)
+    assert best["tile_units"] in (256, 512, 1024, 2048, 4096, 8192) and best["waves_per_simd"] in (2, 3, 4, 6)
+    assert best["gang_waves"] in (1, 4, 8) and best["wide_stores"] in (1, 2)
     assert ms > 0
     for a, b in zip(A.streams, before):
         assert torch.equal(a, b)
@@ -219,7 +224,8 @@ def test_batch_autotune_leaves_streams_and_stays_exact():
         assert torch.equal(A.streams[i], B.streams[i])
 
 
-@pytest.mark.parametrize("cfg", [None, dict(tile_units=1024, waves_per_simd=2, gang_waves=4)], ids=str)
+@pytest.mark.parametrize("cfg", [None, dict(tile_units=1024, waves_per_simd=2, gang_waves=4),
+                                 dict(tile_units=512, waves_per_simd=4, gang_waves=4, wide_stores=2)], ids=str)
 def test_batched_config_full_size(cfg):
     """4096 requests, lengths log-uniform in [1e3, 1e7], 64-1024 streams each,
     random mix of f32/f64 and uniform/normal/exponential: the batch equals
