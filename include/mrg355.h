@@ -360,7 +360,7 @@ typedef struct {
  *                   class (normal, exponential, uniform/raw); 2, 4 or 8 = a
  *                   block of that many waves takes a gang of that many tiles
  *                   -- neighbouring stream blocks of one request -- and its
- *                   waves write each row together (a barrier per row), from
+ *                   waves write rows together (a barrier every three rows), from
  *                   one queue that interleaves the classes              */
 typedef struct {
     uint32_t tile_units;
