@@ -308,7 +308,7 @@ mrg_status mrg_generate_paper(mrg_generator gen, mrg_stream* dev, size_t n_strea
     L.dist = static_cast<int>(dist);
     L.dtype = static_cast<int>(dtype);
     L.param = dist == MRG_EXPONENTIAL ? 1.0 / param : 1.0;
-    plan_paper(L);
+    plan_paper(L, gid(gen));
     hipError_t e = launch_paper(L, gid(gen), stream);
     if (e != hipSuccess) return hip_fail(e, "paper-geometry launch");
     return ok();

@@ -146,12 +146,14 @@ struct PaperLaunch {
     uint32_t nrow, ncol; // the block written
     uint32_t G0, G1;     // work-item lattice
     uint32_t lanes_g1;   // G1, or G1/2 pairs for normals
-    uint32_t rows_per;   // work-item rows per lane
-    uint32_t n_rb;       // row blocks per work-item
+    uint32_t rows_per;   // a lane's chunk: rows_per of its work-item's rows ...
+    uint32_t n_rb;       // ... in n_rb row blocks,
+    uint32_t cols_per;   // and cols_per of each row's visits (cols_per < all only with rows_per = 1) ...
+    uint32_t n_cb;       // ... in n_cb column blocks
     int dist, dtype;
     double param;        // 1/rate for exponentials
 };
-void plan_paper(PaperLaunch& L);
+void plan_paper(PaperLaunch& L, int gen);
 hipError_t launch_paper(const PaperLaunch& L, int gen, hipStream_t s);
 
 // Diagnostics (mrg_selfcheck.hip, mrg_kernels.hip).

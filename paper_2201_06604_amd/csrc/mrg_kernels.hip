@@ -40,6 +40,7 @@ static constexpr JumpTables kHostTab31 = make_jump_tables<kGen31k3p>();
 __constant__ StreamDigits g_dig = make_stream_digits<kGen32k3a>(kHostTab);
 __constant__ StreamDigits g_dig31 = make_stream_digits<kGen31k3p>(kHostTab31);
 __constant__ StepDigitsF64 g_stepdig = make_step_digits_f64<kGen32k3a>(kHostTab);
+__constant__ StepDigitsF64 g_stepdig31 = make_step_digits_f64<kGen31k3p>(kHostTab31);
 
 // ------------------------------------------------------------------ jumps
 template <int G>
@@ -73,17 +74,21 @@ __device__ __forceinline__ void dev_jump(uint32_t x[6], uint64_t e) {
         if (e & 1) dev_apply<G>(dev_tab<G>().step_pow2[0][b], dev_tab<G>().step_pow2[1][b], x);
 }
 
-// x <- A^e x for MRG32k3a by base-64 digits of e (wave-uniform): one exact
-// fp64 matrix-vector product per nonzero digit instead of one integer product
-// per set bit.  x canonical in and out.
+// x <- A^e x by base-64 digits of e (wave-uniform): one exact fp64
+// matrix-vector product per nonzero digit instead of one integer product per
+// set bit.  x canonical in and out.
+template <int G = kGen32k3a>
 __device__ __forceinline__ void dev_jump_digits(uint32_t x[6], uint64_t e) {
+    const StepDigitsF64& T = G == kGen32k3a ? g_stepdig : g_stepdig31;
+    constexpr double m1 = G == kGen32k3a ? kM1d : static_cast<double>(kP1);
+    constexpr double m2 = G == kGen32k3a ? kM2d : static_cast<double>(kP2);
     double v1[3] = {static_cast<double>(x[0]), static_cast<double>(x[1]), static_cast<double>(x[2])};
     double v2[3] = {static_cast<double>(x[3]), static_cast<double>(x[4]), static_cast<double>(x[5])};
     for (int d = 0; e; ++d, e >>= 6) {
         const uint32_t v = static_cast<uint32_t>(e & 63);
         if (v) {
-            matvec_f64(g_stepdig.m[d][0][v], v1, kM1d, kInvM1);
-            matvec_f64(g_stepdig.m[d][1][v], v2, kM2d, kInvM2);
+            matvec_f64(T.m[d][0][v], v1, m1, 1.0 / m1);
+            matvec_f64(T.m[d][1][v], v2, m2, 1.0 / m2);
         }
     }
 #pragma unroll
@@ -260,7 +265,7 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
         for (int w = 0; w < 6; ++w) x[w] = rec[w];
         const uint64_t jump = L.offset + u0 * kSpu;
         if (jump) {
-            if constexpr (ARITH == kArithF64) dev_jump_digits(x, jump);
+            if constexpr (ARITH == kArithF64 || ARITH == kArith31) dev_jump_digits<G>(x, jump);
             else dev_jump<G>(x, jump);
         }
         e[i].load(x);
@@ -1263,10 +1268,12 @@ hipError_t launch_generate(const GenLaunch& L, hipStream_t s) {
 // lane runs both streams, U1 from the first, U2 from the second, X and Y to
 // the two adjacent cells.
 //
-// A lane runs one work-item (or pair) over a block of its rows, jumping its
-// stream(s) to the block's first visit; lanes with neighbouring g1 write
-// neighbouring columns of a row.  With one row block the lane writes the
-// state back; otherwise paper_finalize_kernel does, after the launch.
+// A lane runs one work-item (or pair) over a chunk of its visits: a block of
+// its rows, or, where a work-item has fewer rows than the chunks wanted, a
+// block of one row's visits.  Lanes with neighbouring g1 write neighbouring
+// columns of the same rows in step.  The lane jumps its stream(s) to the
+// chunk's first visit; with one chunk per work-item it writes the state back,
+// otherwise paper_finalize_kernel does, after the launch.
 template <int G>
 struct EngineOf {
     using T = F64Engine;
@@ -1281,46 +1288,66 @@ __device__ __forceinline__ uint64_t paper_stream_of(int dist, uint32_t g0, uint3
                                               : static_cast<uint64_t>(g0) * G1 + g1;
 }
 
+// Advance a stream record by e steps (e wave-uniform) by the fp64 digit tables.
+template <int G>
+__device__ __forceinline__ void paper_jump(uint32_t x[6], uint64_t e) {
+    dev_jump_digits<G>(x, e);
+}
+
+__host__ __device__ inline uint64_t paper_lanes_per_chunk(const PaperLaunch& L) {
+    return (static_cast<uint64_t>(L.G0) * L.lanes_g1 + 63) / 64 * 64;
+}
+
 template <int DIST, int DTYPE, int G>
 __global__ void __launch_bounds__(256) paper_kernel(PaperLaunch L) {
     if constexpr ((DIST == kNormal || DIST == kExponential) && DTYPE == kF64) stage_tables();
     using Engine = typename EngineOf<G>::T;
     using T = typename ElemOf<DTYPE>::T;
     const uint64_t id = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const uint64_t per_block = static_cast<uint64_t>(L.G0) * L.lanes_g1;
-    if (id >= per_block * L.n_rb) return;
-    const uint32_t rb = static_cast<uint32_t>(id / per_block);
-    const uint64_t rem = id % per_block;
+    // lanes per chunk, a whole number of waves: every wave lies in one chunk,
+    // so the chunk and its jump exponents are wave-uniform (scalar table reads)
+    const uint64_t per_chunk = paper_lanes_per_chunk(L);
+    if (id >= per_chunk * L.n_rb * L.n_cb) return;
+    const uint32_t ch = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(id / per_chunk));
+    const uint32_t rb = ch / L.n_cb, cb = ch % L.n_cb;
+    const uint64_t rem = id % per_chunk;
+    if (rem >= static_cast<uint64_t>(L.G0) * L.lanes_g1) return;  // padding of the last wave
     const uint32_t g0 = static_cast<uint32_t>(rem / L.lanes_g1);
     const uint32_t h = static_cast<uint32_t>(rem % L.lanes_g1);
     const uint32_t g1 = DIST == kNormal ? 2 * h : h;
     if (g0 >= L.nrow || g1 >= L.ncol) return;  // the work-item owns no cell
     const uint32_t nr = (L.nrow - 1 - g0) / L.G0 + 1;
     const uint32_t nc = (L.ncol - 1 - g1) / L.G1 + 1;
-    const uint32_t i0 = rb * L.rows_per;
-    if (i0 >= nr) return;
-    const uint32_t i1 = min(nr, i0 + L.rows_per);
-    const uint64_t first = static_cast<uint64_t>(i0) * nc;  // visits before this block
+    const uint32_t nc_max = (L.ncol - 1) / L.G1 + 1;  // nc is nc_max or nc_max - 1
+    const uint32_t i0 = rb * L.rows_per, j0 = cb * L.cols_per;
+    if (i0 >= nr || j0 >= nc) return;
+    const uint32_t i1 = min(nr, i0 + L.rows_per), j1 = min(nc, j0 + L.cols_per);
 
+    // visits before the chunk: i0 nc + j0 = [i0 (nc_max - 1) + j0] + [i0 if nc == nc_max],
+    // two jumps with wave-uniform exponents
+    const uint64_t e_all = static_cast<uint64_t>(i0) * (nc_max - 1) + j0;
+    const bool longer = nc == nc_max && i0 > 0;
     uint32_t* ra = L.streams + paper_stream_of(DIST, g0, g1, L.G0, L.G1) * 18;
     uint32_t* rb_rec = DIST == kNormal ? L.streams + paper_stream_of(DIST, g0, g1 + 1, L.G0, L.G1) * 18 : ra;
     uint32_t x[6];
     Engine ea, eb;
 #pragma unroll
     for (int w = 0; w < 6; ++w) x[w] = ra[w];
-    if (first) dev_jump<G>(x, first);
+    if (e_all) paper_jump<G>(x, e_all);
+    if (longer) paper_jump<G>(x, i0);
     ea.load(x);
     if constexpr (DIST == kNormal) {
 #pragma unroll
         for (int w = 0; w < 6; ++w) x[w] = rb_rec[w];
-        if (first) dev_jump<G>(x, first);
+        if (e_all) paper_jump<G>(x, e_all);
+        if (longer) paper_jump<G>(x, i0);
         eb.load(x);
     }
     T* out = static_cast<T*>(L.out);
     const double inv_rate = L.param;
     for (uint32_t i = i0; i < i1; ++i) {
-        T* row = out + static_cast<uint64_t>(g0 + static_cast<uint64_t>(i) * L.G0) * L.npad;
-        for (uint32_t j = 0, c = g1; j < nc; ++j, c += L.G1) {
+        T* row = out + (g0 + static_cast<uint64_t>(i) * L.G0) * L.npad;
+        for (uint32_t j = j0, c = g1 + j0 * L.G1; j < j1; ++j, c += L.G1) {
             if constexpr (DIST == kNormal) {
                 auto z1 = ea.step_rot();
                 auto z2 = eb.step_rot();
@@ -1332,8 +1359,9 @@ __global__ void __launch_bounds__(256) paper_kernel(PaperLaunch L) {
                 __builtin_nontemporal_store(value1<DIST, DTYPE, G>(ea.step_rot(), inv_rate), row + c);
             }
         }
+        if (L.n_cb > 1) break;  // a column block covers one row
     }
-    if (L.n_rb == 1) {
+    if (L.n_rb == 1 && L.n_cb == 1) {
         ea.save(x);
 #pragma unroll
         for (int w = 0; w < 6; ++w) ra[w] = x[w];
@@ -1345,8 +1373,8 @@ __global__ void __launch_bounds__(256) paper_kernel(PaperLaunch L) {
     }
 }
 
-// After a launch with several row blocks: every used stream advances by its
-// work-item's number of visits.
+// After a launch with several chunks per work-item: every used stream
+// advances by its work-item's number of visits.
 template <int G>
 __global__ void __launch_bounds__(256) paper_finalize_kernel(PaperLaunch L) {
     const uint64_t id = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1369,23 +1397,79 @@ __global__ void __launch_bounds__(256) paper_finalize_kernel(PaperLaunch L) {
     }
 }
 
-void plan_paper(PaperLaunch& L) {
+template <int DIST, int DTYPE, int G>
+static int paper_blocks_per_cu() {
+    static const int cached = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &n, reinterpret_cast<const void*>(paper_kernel<DIST, DTYPE, G>), 256, 0) != hipSuccess || n <= 0)
+            n = 1;
+        return n;
+    }();
+    return cached;
+}
+
+template <int G>
+static int paper_blocks_per_cu_g(int dist, int dtype) {
+    switch (dist) {
+        case kUniform: return dtype == kF64 ? paper_blocks_per_cu<kUniform, kF64, G>()
+                                            : paper_blocks_per_cu<kUniform, kF32, G>();
+        case kNormal: return dtype == kF64 ? paper_blocks_per_cu<kNormal, kF64, G>()
+                                           : paper_blocks_per_cu<kNormal, kF32, G>();
+        case kExponential: return dtype == kF64 ? paper_blocks_per_cu<kExponential, kF64, G>()
+                                                : paper_blocks_per_cu<kExponential, kF32, G>();
+        default: return paper_blocks_per_cu<kRaw, kU32, G>();
+    }
+}
+
+// Chunks per work-item: about as many as fill a whole number of rounds of
+// the waves the device holds at once -- one for normals and exponentials, so
+// that every lane runs one chunk of about equal length and no partly filled
+// round trails the launch, three for uniforms and raw words, whose stores
+// keep more waves busy over time -- in whole rows while a work-item has
+// enough of them, else in blocks of one row's visits.  The 10^4 x 10^4
+// normals of Section 3.1 on a 512 x 128 lattice (32,768 pairs, 20 rows of
+// 78-79 visits each): 0.29 ms against 0.41 ms in one-row blocks for 2^20
+// lanes with per-bit jumps; fp64 uniforms 0.165 against 0.18 ms.
+#ifndef MRG_PAPER_ROUNDS
+#define MRG_PAPER_ROUNDS 1
+#endif
+#ifndef MRG_PAPER_ROUNDS_PLAIN
+#define MRG_PAPER_ROUNDS_PLAIN 3
+#endif
+constexpr uint64_t kPaperRounds = MRG_PAPER_ROUNDS;             // normals, exponentials
+constexpr uint64_t kPaperRoundsPlain = MRG_PAPER_ROUNDS_PLAIN;  // uniforms, raw (store-bound)
+
+void plan_paper(PaperLaunch& L, int gen) {
     L.lanes_g1 = L.dist == kNormal ? L.G1 / 2 : L.G1;
     const uint64_t nr_max = (static_cast<uint64_t>(L.nrow) + L.G0 - 1) / L.G0;
-    const uint64_t items = static_cast<uint64_t>(L.G0) * L.lanes_g1;
-    // about 2^20 lanes (16 waves per SIMD), at least one row per lane
-    uint64_t blocks = ((1ull << 20) + items - 1) / items;
-    if (blocks > nr_max) blocks = nr_max;
-    if (blocks < 1) blocks = 1;
-    L.rows_per = static_cast<uint32_t>((nr_max + blocks - 1) / blocks);
-    if (L.rows_per == 0) L.rows_per = 1;
-    L.n_rb = static_cast<uint32_t>((nr_max + L.rows_per - 1) / L.rows_per);
+    const uint64_t nc_max = (static_cast<uint64_t>(L.ncol) + L.G1 - 1) / L.G1;
+    const uint64_t items = paper_lanes_per_chunk(L);
+    const int per_cu = gen == kGen31k3p ? paper_blocks_per_cu_g<kGen31k3p>(L.dist, L.dtype)
+                                        : paper_blocks_per_cu_g<kGen32k3a>(L.dist, L.dtype);
+    const uint64_t resident = static_cast<uint64_t>(device_cu_count()) * static_cast<uint64_t>(per_cu) * 256;
+    const uint64_t rounds = L.dist == kUniform || L.dist == kRaw ? kPaperRoundsPlain : kPaperRounds;
+    const uint64_t want = std::max<uint64_t>(1, rounds * resident / std::max<uint64_t>(1, items));
+    if (want <= nr_max || nc_max <= 1) {
+        L.rows_per = static_cast<uint32_t>((nr_max + want - 1) / want);
+        if (L.rows_per == 0) L.rows_per = 1;
+        L.n_rb = static_cast<uint32_t>((nr_max + L.rows_per - 1) / L.rows_per);
+        L.cols_per = static_cast<uint32_t>(nc_max);
+        L.n_cb = 1;
+    } else {
+        L.rows_per = 1;
+        L.n_rb = static_cast<uint32_t>(nr_max);
+        const uint64_t per_row = std::min<uint64_t>(nc_max, (want + nr_max - 1) / nr_max);
+        L.cols_per = static_cast<uint32_t>((nc_max + per_row - 1) / per_row);
+        L.n_cb = static_cast<uint32_t>((nc_max + L.cols_per - 1) / L.cols_per);
+    }
     if (L.n_rb == 0) L.n_rb = 1;
+    if (L.n_cb == 0) L.n_cb = 1;
 }
 
 template <int DIST, int DTYPE>
 static hipError_t launch_paper_t(const PaperLaunch& L, int gen, hipStream_t s) {
-    const uint64_t lanes = static_cast<uint64_t>(L.G0) * L.lanes_g1 * L.n_rb;
+    const uint64_t lanes = paper_lanes_per_chunk(L) * L.n_rb * L.n_cb;
     const dim3 grid(static_cast<unsigned>((lanes + 255) / 256));
     if (gen == kGen32k3a) hipLaunchKernelGGL((paper_kernel<DIST, DTYPE, kGen32k3a>), grid, dim3(256), 0, s, L);
     else hipLaunchKernelGGL((paper_kernel<DIST, DTYPE, kGen31k3p>), grid, dim3(256), 0, s, L);
@@ -1408,7 +1492,7 @@ hipError_t launch_paper(const PaperLaunch& L, int gen, hipStream_t s) {
         default:
             e = launch_paper_t<kRaw, kU32>(L, gen, s);
     }
-    if (e != hipSuccess || L.n_rb == 1) return e;
+    if (e != hipSuccess || (L.n_rb == 1 && L.n_cb == 1)) return e;
     const uint64_t items = static_cast<uint64_t>(L.G0) * L.lanes_g1;
     const dim3 grid(static_cast<unsigned>((items + 255) / 256));
     if (gen == kGen32k3a) hipLaunchKernelGGL(paper_finalize_kernel<kGen32k3a>, grid, dim3(256), 0, s, L);
