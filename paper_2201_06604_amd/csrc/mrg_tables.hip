@@ -5,7 +5,7 @@
 //
 // Each entry is sampled by hyper_invert_ck (mrg_hyper.h): the inversion that
 // the oracle defines, with two shortcuts that give the same bits; the
-// checkpoints of its search live in LDS, 8 per lane.
+// checkpoints of its search live in LDS.
 //
 // One lane owns one table.  The loops' trip counts depend on the margins, so
 // lanes of a wave diverge; that is the price of exact inversion.
@@ -22,7 +22,20 @@
 
 namespace mrg355 {
 
-constexpr int kCk = 8;         // inversion checkpoints per lane (LDS)
+// Inversion checkpoints per lane (LDS, 20 bytes each).  More shorten the
+// second pass of a wide search but hold LDS that would otherwise let more
+// blocks run: 10^6 tables of totals 5..200 took 2.27 / 2.25 / 2.12 / 2.06 /
+// 2.39 ms with 3 / 4 / 5 / 6 / 8 (6: five blocks per CU); the paper's Fisher
+// tables (totals about 12,900) 41.4 / 38.8 / 45.9 / 43.7 ms (Table 1) with
+// 6 / 8 / 12 / 16.
+#ifndef MRG_TABLE_CK
+#define MRG_TABLE_CK 6
+#endif
+#ifndef MRG_FISHER_CK
+#define MRG_FISHER_CK 8
+#endif
+constexpr int kTablesCk = MRG_TABLE_CK;
+constexpr int kFisherCk = MRG_FISHER_CK;
 constexpr int kTableBlock = 256;
 
 // log(n!) for n <= kTableMaxTotal: lgamma(n+1) in long double on the host,
@@ -35,7 +48,7 @@ __device__ __forceinline__ double log_factorial(int n) { return g_logfact[n]; }
 // One I x J table (I, J <= MAXD) with row totals r[], column totals c[]:
 // entries to tab[i*ld + j] (when tab is not null); returns -sum log(n_ij!)
 // summed row-major.  The engine advances (I-1)(J-1) steps.
-template <int MAXD, typename Engine>
+template <int MAXD, int NCK, typename Engine>
 __device__ double sample_table(Engine& e, double norm, int I, int J, const int32_t* r, const int32_t* c, int32_t* tab,
                                int ld, HyperCk ck) {
     int32_t crem[MAXD];
@@ -47,7 +60,7 @@ __device__ double sample_table(Engine& e, double norm, int I, int J, const int32
         for (int j = 0; j < J; ++j) Np += crem[j];
         for (int j = 0; j < J - 1; ++j) {
             const double u = to_f64(e.step_rot()) * norm;
-            const int x = hyper_invert_ck<kCk>(u, Np, crem[j], rrem, ck);
+            const int x = hyper_invert_ck<NCK>(u, Np, crem[j], rrem, ck);
             if (tab) tab[i * ld + j] = x;
             stat -= log_factorial(x);
             rrem -= x;
@@ -111,7 +124,7 @@ __device__ __forceinline__ void one_table(uint64_t t, uint32_t* streams, const i
     for (int w = 0; w < 6; ++w) x[w] = rec[w];
     typename GenOf<G>::Engine e;
     e.load(x);
-    const double stat = sample_table<5>(e, GenOf<G>::norm, It, Jt, rows + t * 5, cols + t * 5, out, 5, ck);
+    const double stat = sample_table<5, kTablesCk>(e, GenOf<G>::norm, It, Jt, rows + t * 5, cols + t * 5, out, 5, ck);
     if (stats) stats[t] = stat;
     e.save(x);
 #pragma unroll
@@ -131,8 +144,8 @@ template <int G>
 __global__ void __launch_bounds__(kTableBlock) tables_kernel(uint32_t* streams, uint64_t n, const int32_t* I,
                                                              const int32_t* J, const int32_t* rows, const int32_t* cols,
                                                              int32_t* tabs, double* stats) {
-    __shared__ double ck_s[kCk * kTableBlock], ck_w[kCk * kTableBlock];
-    __shared__ int ck_r[kCk * kTableBlock];
+    __shared__ double ck_s[kTablesCk * kTableBlock], ck_w[kTablesCk * kTableBlock];
+    __shared__ int ck_r[kTablesCk * kTableBlock];
     constexpr int kBuckets = 64;
     __shared__ uint16_t order[kTableBlock];
     __shared__ uint32_t start[kBuckets + 1];
@@ -183,8 +196,8 @@ struct FisherArgs {
 // lane executes it, with the wave's count on lane 0 and 0 elsewhere).
 template <int G>
 __global__ void __launch_bounds__(kTableBlock) fisher_kernel(FisherArgs a) {
-    __shared__ double ck_s[kCk * kTableBlock], ck_w[kCk * kTableBlock];
-    __shared__ int ck_r[kCk * kTableBlock];
+    __shared__ double ck_s[kFisherCk * kTableBlock], ck_w[kFisherCk * kTableBlock];
+    __shared__ int ck_r[kFisherCk * kTableBlock];
     const HyperCk ck{ck_s + threadIdx.x, ck_w + threadIdx.x, ck_r + threadIdx.x, kTableBlock};
     const uint64_t b = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint32_t lane = threadIdx.x & 63;
@@ -196,7 +209,8 @@ __global__ void __launch_bounds__(kTableBlock) fisher_kernel(FisherArgs a) {
         for (int w = 0; w < 6; ++w) x[w] = rec[w];
         typename GenOf<G>::Engine e;
         e.load(x);
-        const double stat = sample_table<kFisherMaxDim>(e, GenOf<G>::norm, a.I, a.J, a.r, a.c, nullptr, 0, ck);
+        const double stat =
+            sample_table<kFisherMaxDim, kFisherCk>(e, GenOf<G>::norm, a.I, a.J, a.r, a.c, nullptr, 0, ck);
         hit = stat <= a.threshold;
         if (a.stats) a.stats[b] = stat;
         e.save(x);
