@@ -25,11 +25,11 @@ S_STREAMS = 262144
 PER_STREAM = 4096
 N = S_STREAMS * PER_STREAM
 HBM_PEAK_GBPS = 8000.0
-# every source the generate kernel is compiled from: counters taken before a
-# change to any of them no longer describe the kernel
+# every source the profiled kernels are compiled or planned from: counters
+# taken before a change to any of them no longer describe the kernels
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2201_06604_amd", "csrc", f)
                for f in ("mrg_kernels.hip", "mrg_engine.h", "mrg_math.h", "mrg_internal.h", "mrg_logtab.h",
-                         "mrg_sincostab.h", "mrg_tuned.h")]
+                         "mrg_sincostab.h", "mrg_tuned.h", "mrg_tables.hip", "mrg_hyper.h", "mrg_batch.cpp")]
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "gen_kernel_uniform_f64_262144x4096_traffic.json")
 COPY_PROBE_BYTES = 1 << 30
 # VALU issue ceiling: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one lane-instruction

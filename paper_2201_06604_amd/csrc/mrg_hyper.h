@@ -47,6 +47,10 @@ struct HyperCk {
     int stride;
 };
 
+// The integer products of the ratio are formed in fp64: with every total at
+// most 2^20 (the callers' bound) each factor is an integer below 2^21 and each
+// product below 2^42, so the fp64 products are exact and equal the integer
+// products converted to double.
 template <int NCK>
 MRG_HD inline int hyper_invert_ck(double u, int64_t Np, int64_t K, int64_t n, HyperCk ck) {
     int64_t lo = n - (Np - K);
@@ -54,11 +58,14 @@ MRG_HD inline int hyper_invert_ck(double u, int64_t Np, int64_t K, int64_t n, Hy
     const int64_t hi = n < K ? n : K;
     if (hi <= lo) return static_cast<int>(lo);
     const int64_t step = (hi - lo + NCK) / NCK;  // ceil(span / NCK), span = hi - lo + 1
+    const double Kd = static_cast<double>(K), nd = static_cast<double>(n);
+    const double rest = static_cast<double>(Np - K - n + 1);  // N' - K - n + 1
     int64_t next = lo;
     int nck = 0;
     double W = 0.0, w = 1.0;
     int scales = 0;
-    for (int64_t x = lo; x <= hi; ++x) {
+    double xd = static_cast<double>(lo);
+    for (int64_t x = lo; x <= hi; ++x, xd += 1.0) {
         if (x == next) {
             ck.s[nck * ck.stride] = W;
             ck.w[nck * ck.stride] = w;
@@ -68,8 +75,8 @@ MRG_HD inline int hyper_invert_ck(double u, int64_t Np, int64_t K, int64_t n, Hy
         }
         W += w;
         if (x < hi) {
-            const double num = static_cast<double>((K - x) * (n - x));
-            const double den = static_cast<double>((x + 1) * (Np - K - n + x + 1));
+            const double num = (Kd - xd) * (nd - xd);
+            const double den = (xd + 1.0) * (rest + xd);
             w = w * num / den;
             if (w > kHyperBig) {
                 w = ldexp(w, -kHyperScaleExp);
@@ -88,11 +95,12 @@ MRG_HD inline int hyper_invert_ck(double u, int64_t Np, int64_t K, int64_t n, Hy
     double s = ck.s[c * ck.stride];
     w = ck.w[c * ck.stride];
     int done = ck.r[c * ck.stride];
-    for (int64_t x = lo + c * step; x <= hi; ++x) {
+    xd = static_cast<double>(lo + c * step);
+    for (int64_t x = lo + c * step; x <= hi; ++x, xd += 1.0) {
         s += w;
         if (target <= ldexp(s, -kHyperScaleExp * (scales - done))) return static_cast<int>(x);
-        const double num = static_cast<double>((K - x) * (n - x));
-        const double den = static_cast<double>((x + 1) * (Np - K - n + x + 1));
+        const double num = (Kd - xd) * (nd - xd);
+        const double den = (xd + 1.0) * (rest + xd);
         w = w * num / den;
         if (w > kHyperBig) {
             w = ldexp(w, -kHyperScaleExp);
