@@ -97,6 +97,36 @@ def test_tables_degenerate_cases():
     np.testing.assert_array_equal(after[:2], rec[:2])  # no draws
 
 
+def test_tables_at_the_total_bound():
+    """Tables whose grand total is the largest accepted, 2^20: the ratio of
+    consecutive hypergeometric weights multiplies factors up to 2^20, the
+    largest products the kernel forms in fp64 (below 2^42, exact), and the
+    searches span hundreds of thousands of values.  Sixteen tables of random
+    shapes and margins, bit-exact with the oracle."""
+    rng = np.random.default_rng(2201066)
+    n, total = 16, 1 << 20
+    I = rng.integers(2, 6, size=n).astype(np.int32)
+    J = rng.integers(2, 6, size=n).astype(np.int32)
+    rows = np.zeros((n, 5), dtype=np.int32)
+    cols = np.zeros((n, 5), dtype=np.int32)
+
+    def composition(k):  # k positive parts summing to total
+        cuts = np.sort(rng.choice(np.arange(1, total), size=k - 1, replace=False))
+        return np.diff(np.concatenate(([0], cuts, [total])))
+
+    for t in range(n):
+        rows[t, :I[t]] = composition(I[t])
+        cols[t, :J[t]] = composition(J[t])
+    rec = _records(workloads.random_seed(23), n)
+    tabs, stats, after = _run_tables(rec, I, J, rows, cols)
+    work = rec.copy()
+    wtabs, wstats = O.tables(GEN, work, I, J, rows, cols)
+    np.testing.assert_array_equal(tabs, wtabs)
+    np.testing.assert_array_equal(after, work)
+    _check_stats(stats, wstats)
+    assert (tabs.reshape(n, -1).sum(axis=1) == total).all()
+
+
 def test_tables_invalid_margins_leave_stream():
     """Unequal sums, a negative margin, a shape out of range or a total above
     2^20 give zeros, a NaN statistic and an untouched stream; valid tables in
