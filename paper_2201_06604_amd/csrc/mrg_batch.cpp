@@ -38,6 +38,7 @@ struct mrg_batch_plan {
     double cls_cost[kClasses];
     uint32_t n_gangs;  // gang mode: tiles holds n_gangs * gang entries (padding: req = kNoRequest)
     uint32_t narrow;   // every request runs one stream per lane (the narrow gang kernel serves it)
+    uint32_t xq_lo[kXcdQueues + 1];  // gang mode: the gangs of each XCD's queue
     std::vector<uint32_t> fin_req;
     std::vector<uint64_t> fin_pre;
     uint64_t fin_total;
@@ -139,6 +140,8 @@ void order_gangs(mrg_batch_plan& P, const std::vector<double>& cost, const std::
         double key;
         int cls;
         uint32_t first;  // index into `member`
+        double cost;
+        uint32_t req;    // the request of its first tile
     };
     std::vector<Gang> gangs;
     std::vector<uint32_t> member;  // tile indices, G per gang, kNoRequest for padding
@@ -158,7 +161,7 @@ void order_gangs(mrg_batch_plan& P, const std::vector<double>& cost, const std::
         double done = 0.0;
         for (size_t g = 0; g < n_g; ++g) {
             gangs.push_back(Gang{total > 0 ? (done + 0.5 * gcost[g]) / total : 0.0, c,
-                                 static_cast<uint32_t>(member.size())});
+                                 static_cast<uint32_t>(member.size()), gcost[g], P.tiles[v[g * G]].req});
             done += gcost[g];
             for (uint32_t w = 0; w < G; ++w) {
                 const size_t k = g * G + w;
@@ -170,13 +173,38 @@ void order_gangs(mrg_batch_plan& P, const std::vector<double>& cost, const std::
         if (a.key != b.key) return a.key < b.key;
         return a.cls < b.cls;
     });
+    // Every request's gangs go to one XCD's queue (the lines its gangs share
+    // are then completed in one L2): requests by estimated work, longest
+    // first, each to the least loaded XCD; each queue keeps the merged order.
+    std::vector<double> req_cost(P.reqs.size(), 0.0);
+    for (const Gang& g : gangs) req_cost[g.req] += g.cost;
+    std::vector<uint32_t> by_cost(P.reqs.size());
+    for (uint32_t r = 0; r < by_cost.size(); ++r) by_cost[r] = r;
+    std::stable_sort(by_cost.begin(), by_cost.end(), [&](uint32_t a, uint32_t b) { return req_cost[a] > req_cost[b]; });
+    std::vector<uint8_t> xcd_of(P.reqs.size(), 0);
+    double load[kXcdQueues] = {};
+    for (uint32_t r : by_cost) {
+        int best = 0;
+        for (int x = 1; x < kXcdQueues; ++x)
+            if (load[x] < load[best]) best = x;
+        xcd_of[r] = static_cast<uint8_t>(best);
+        load[best] += req_cost[r];
+    }
     std::vector<BatchTile> out;
     out.reserve(gangs.size() * G);
-    for (const Gang& g : gangs)
-        for (uint32_t w = 0; w < G; ++w) {
-            const uint32_t t = member[g.first + w];
-            out.push_back(t == kNoRequest ? BatchTile{kNoRequest, 0, 0, 0} : P.tiles[t]);
+    P.xq_lo[0] = 0;
+    for (int x = 0; x < kXcdQueues; ++x) {
+        uint32_t n = 0;
+        for (const Gang& g : gangs) {
+            if (xcd_of[g.req] != x) continue;
+            ++n;
+            for (uint32_t w = 0; w < G; ++w) {
+                const uint32_t t = member[g.first + w];
+                out.push_back(t == kNoRequest ? BatchTile{kNoRequest, 0, 0, 0} : P.tiles[t]);
+            }
         }
+        P.xq_lo[x + 1] = P.xq_lo[x] + n;
+    }
     P.tiles.swap(out);
     P.n_gangs = static_cast<uint32_t>(gangs.size());
     for (int c = 0; c <= kClasses; ++c) P.tile_lo[c] = 0;
@@ -324,6 +352,7 @@ BatchLaunch launch_args(const mrg_batch_plan& P, void* ws) {
     B.fin_total = P.fin_total;
     B.n_gangs = P.n_gangs;
     B.narrow = P.narrow;
+    for (int x = 0; x <= kXcdQueues; ++x) B.xq_lo[x] = P.n_gangs ? P.xq_lo[x] : 0;
     for (int c = 0; c <= kClasses; ++c) B.tile_lo[c] = P.tile_lo[c];
     return B;
 }

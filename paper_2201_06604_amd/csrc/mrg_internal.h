@@ -69,8 +69,10 @@ inline int batch_kind_class(int kind) {
     return kClsPlain;
 }
 
+constexpr int kXcdQueues = 8;  // gang mode: one gang queue per XCD (block b runs on XCD b mod 8)
+
 struct BatchHeader {    // at workspace offset 0, reset by every launch
-    uint32_t queue[4];  // next tile to hand out, per class
+    uint32_t queue[kXcdQueues];  // next tile (class queues) or gang (per XCD) to hand out
     uint64_t t_start;   // device real-time clock when the persistent kernel started
 };
 
@@ -90,6 +92,7 @@ struct BatchLaunch {    // kernel arguments
     uint32_t n_gangs;                 // gang mode: tiles[g*wpb .. g*wpb+wpb-1] is gang g; 0 = class queues
     uint32_t grid;                    // blocks of the persistent kernel
     uint32_t narrow;                  // gang mode: 1 = every tile is of one stream per lane
+    uint32_t xq_lo[kXcdQueues + 1];   // gang mode: XCD x's queue holds gangs [xq_lo[x], xq_lo[x+1])
 };
 
 hipError_t launch_batch(const BatchLaunch& B, unsigned grid, unsigned block, hipStream_t s);

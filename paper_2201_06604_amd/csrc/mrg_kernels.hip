@@ -466,8 +466,13 @@ __global__ void __launch_bounds__(256) finalize_kernel(uint32_t* streams, uint32
 __global__ void __launch_bounds__(256) batch_init_kernel(BatchLaunch B) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0 && B.n_gangs) {
-        // gang mode: block b starts on gang b, the queue hands out the rest
-        B.head->queue[0] = B.grid;
+        // gang mode: block b, the (b / 8)-th block on XCD b mod 8, starts on
+        // that XCD's gang b / 8; each XCD's queue hands out the rest
+        for (int x = 0; x < kXcdQueues; ++x) {
+            const uint32_t blocks = B.grid > static_cast<uint32_t>(x) ? (B.grid - x + kXcdQueues - 1) / kXcdQueues : 0;
+            const uint32_t count = B.xq_lo[x + 1] - B.xq_lo[x];
+            B.head->queue[x] = blocks < count ? blocks : count;
+        }
         B.head->t_start = 0;
     } else if (i == 0) {
         // tiles [0, waves of the class) are taken without the queue (each
@@ -477,7 +482,7 @@ __global__ void __launch_bounds__(256) batch_init_kernel(BatchLaunch B) {
             const uint32_t count = B.tile_lo[c + 1] - B.tile_lo[c];
             B.head->queue[c] = waves < count ? waves : count;
         }
-        B.head->queue[kClasses] = 0;
+        for (int c = kClasses; c < kXcdQueues; ++c) B.head->queue[c] = 0;
         B.head->t_start = 0;
     }
     if (i < B.n_req) {
@@ -685,11 +690,15 @@ __device__ __forceinline__ uint32_t tile_iters(const BatchLaunch& B, const Batch
     return __builtin_amdgcn_readfirstlane(static_cast<uint32_t>((kend - u0) / 3));
 }
 
-// Blocks take gangs from one counter (the first gang of block b is b).  The
-// gang index travels through LDS: wave 0 takes it (every lane executes the
-// atomic, increment 1 on lane 0 only), and two barriers bracket the read so
-// that no wave can overwrite it before every wave has read it.  All control
-// flow around the barriers is block-uniform.
+// Gangs come from one queue per XCD: the host gives each request's gangs to
+// one XCD, so that the lines two of its gangs share are completed in that
+// XCD's L2, and a block takes its own XCD's gangs first (block b runs on XCD
+// b mod 8, the (b / 8)-th there, and starts on that list's gang b / 8), then
+// those of the others in turn until every list is empty.  The gang index
+// travels through LDS: wave 0 takes it (every lane executes the atomics,
+// increment 1 on lane 0 only), and two barriers bracket the read so that no
+// wave can overwrite it before every wave has read it.  All control flow
+// around the barriers is block-uniform.
 //
 // NARROW: the plan holds only tiles of one stream per lane.  Their code alone
 // fits the registers of six resident waves per SIMD, where the code of every
@@ -702,8 +711,27 @@ __device__ __forceinline__ void gang_loop(const BatchLaunch& B) {
     const uint32_t one = lane == 0 ? 1u : 0u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (blockIdx.x == 0 && threadIdx.x < 64) B.head->t_start = __builtin_amdgcn_s_memrealtime();
-    uint32_t g = blockIdx.x;
-    while (g < B.n_gangs) {
+    constexpr uint32_t kFetch = 0xfffffffeu, kNone = 0xffffffffu;
+    const uint32_t home = blockIdx.x % kXcdQueues;
+    const uint32_t rank = blockIdx.x / kXcdQueues;
+    uint32_t g = rank < B.xq_lo[home + 1] - B.xq_lo[home] ? B.xq_lo[home] + rank : kFetch;
+    for (;;) {
+        if (g == kFetch) {
+            if (wave == 0) {
+                uint32_t nxt = kNone;
+                for (uint32_t y = 0; y < kXcdQueues && nxt == kNone; ++y) {
+                    const uint32_t x = (home + y) % kXcdQueues;
+                    const uint32_t count = B.xq_lo[x + 1] - B.xq_lo[x];
+                    const uint32_t q = __builtin_amdgcn_readfirstlane(atomicAdd(&B.head->queue[x], one));
+                    if (q < count) nxt = B.xq_lo[x] + q;
+                }
+                next_gang = nxt;
+            }
+            __syncthreads();
+            g = next_gang;
+            __syncthreads();
+        }
+        if (g == kNone) break;
         const BatchTile* gt = B.tiles + static_cast<uint64_t>(g) * B.wpb;
         uint32_t nbar = 0, nit = 0;
         for (uint32_t w = 0; w < B.wpb; ++w) {
@@ -758,13 +786,7 @@ __device__ __forceinline__ void gang_loop(const BatchLaunch& B) {
                 }
             }
         }
-        if (wave == 0) {
-            const uint32_t q = __builtin_amdgcn_readfirstlane(atomicAdd(&B.head->queue[0], one));
-            next_gang = q;
-        }
-        __syncthreads();
-        g = next_gang;
-        __syncthreads();
+        g = kFetch;
     }
 }
 
