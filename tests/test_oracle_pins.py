@@ -355,6 +355,25 @@ def test_placement_rule(dist, dtype, S, n):
         np.testing.assert_array_equal(work[s, 6:], streams[s, 6:])
 
 
+@pytest.mark.parametrize("dist", [O.NORMAL, O.EXPONENTIAL])
+def test_f32_transforms_are_the_f64_values_rounded_to_nearest(dist):
+    """Our reading for fp32 normals and exponentials: the fp64 value of the
+    same draw rounded to the nearest float (numpy's conversion, ties to even),
+    unlike fp32 uniforms, which round toward zero so as never to reach 1.
+    A truncating or toward-zero narrowing would differ on about half of the
+    draws."""
+    seed = workloads.random_seed(9)
+    st = O.create_streams(O.MRG32K3A, seed.copy(), 8)
+    n = 8 * 4001
+    f64 = O.generate(O.MRG32K3A, st.copy(), n, dist, O.F64, 1.5)
+    f32 = O.generate(O.MRG32K3A, st.copy(), n, dist, O.F32, 1.5)
+    assert f32.dtype == np.float32
+    np.testing.assert_array_equal(f32, f64.astype(np.float32))
+    rz = np.where(np.abs(f64.astype(np.float32).astype(np.float64)) > np.abs(f64),
+                  np.nextafter(f64.astype(np.float32), np.float32(0)), f64.astype(np.float32))
+    assert (rz != f32).mean() > 0.3  # the two rules are told apart on this sample
+
+
 def test_normal_pairs_come_from_one_stream():
     """Draws 2p, 2p+1 of a stream are X, Y of Algorithm 1 fed by that stream's
     steps 2p, 2p+1 (our reading of the pairing)."""
