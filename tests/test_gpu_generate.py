@@ -4,8 +4,6 @@ States, uniforms (f64, f32 round-toward-zero) and raw integers must match
 bit for bit.  Normals and exponentials must satisfy
 |gpu - ref| <= tol * max(|ref|, 1) with tol = 1e-15 (f64) and 1e-6 (f32).
 """
-import os
-
 import numpy as np
 import pytest
 
@@ -357,12 +355,10 @@ def test_throughput_config_full_size_sampled(dist, dtype):
     del out
 
 
-@pytest.mark.skipif(os.environ.get("MRG_PARITY_LONG") != "1",
-                    reason="long mode: set MRG_PARITY_LONG=1 to compare all 2^30 numbers")
 def test_throughput_config_every_number():
-    """Long mode: all 2^30 fp64 uniforms of the throughput configuration,
-    compared with the oracle in blocks of 16,384 streams (columns of the
-    k*S + s layout)."""
+    """All 2^30 fp64 uniforms of the throughput configuration, in the launch
+    the benchmark times, compared with the oracle in blocks of 16,384 streams
+    (columns of the k*S + s layout; about 4 s with 16 host threads)."""
     S, per, blk = 262144, 4096, 16384
     seed = workloads.random_seed()
     c = P.mrg_creator_init(seed)
