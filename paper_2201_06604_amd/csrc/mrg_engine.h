@@ -246,10 +246,11 @@ __device__ __forceinline__ void sincospi_unit_series(double t, double* sp, doubl
 // never zero, subnormal or non-finite, so the range scaling and special
 // cases of a general square root are left out.  Goldschmidt's iteration from
 // the hardware reciprocal square root y ~ 1/sqrt(x): g ~ sqrt(x) and
-// h ~ 1/(2 sqrt(x)) are refined together once, then two Newton corrections
-// g += h (x - g^2) with exact residuals (FMA).  mrg_transform_accuracy
+// h ~ 1/(2 sqrt(x)) are refined together once, then one Newton correction
+// g += h (x - g^2) with an exact residual (FMA).  mrg_transform_accuracy
 // compares it with the HIP library's sqrt on the radius argument of any range
-// of generator outputs.
+// of generator outputs: bit-identical over every output of both generators
+// (a second correction changed no result).
 __device__ __forceinline__ double sqrt_radius(double x) {
     const double y = __builtin_amdgcn_rsq(x);
     double g = x * y;
@@ -257,9 +258,7 @@ __device__ __forceinline__ double sqrt_radius(double x) {
     const double r = __builtin_fma(-h, g, 0.5);
     g = __builtin_fma(g, r, g);
     h = __builtin_fma(h, r, h);
-    double d = __builtin_fma(-g, g, x);
-    g = __builtin_fma(d, h, g);
-    d = __builtin_fma(-g, g, x);
+    const double d = __builtin_fma(-g, g, x);
     return __builtin_fma(d, h, g);
 }
 
