@@ -357,8 +357,10 @@ __device__ __forceinline__ void stage_tables() {
 // c_j = cos(pi j/64) from the table as hi + lo,
 // sin(pi t) = s_j + (s_j (cos(pi d) - 1) + c_j sin(pi d))
 // and cos(pi t) = c_j + (c_j (cos(pi d) - 1) - s_j sin(pi d)), where
-// sin(pi d) runs through d^7 and cos(pi d) - 1 through d^8 (the next terms
-// are below 2^-60 of their sums at |d| = 1/128).  On the axes (j a multiple
+// sin(pi d) runs through d^7 and cos(pi d) - 1 through d^6 (the next terms
+// are below 2^-60 of sin(pi d) and 3.3e-18 in absolute value at |d| = 1/128:
+// even where cos(pi t) is smallest beside a nonzero c_j, j = 31 or 33, that is
+// under 2^-57 of the result).  On the axes (j a multiple
 // of 32) the table holds exact zeros and ones, so results near the zeros of
 // sin and cos keep their relative accuracy.  mrg_transform_accuracy compares
 // both results with the HIP library's sincospi over any range of generator
@@ -373,8 +375,7 @@ __device__ __forceinline__ void sincospi_unit(double t, double* sp, double* cp) 
     ps = __builtin_fma(ps, z, -5.16771278004997);   // -pi^3/3!
     ps = __builtin_fma(ps, z, 3.141592653589793);   // pi
     const double sd = d * ps;
-    double pc = 0.2353306303588932;                 // pi^8/8!
-    pc = __builtin_fma(pc, z, -1.3352627688545895); // -pi^6/6!
+    double pc = -1.3352627688545895;                // -pi^6/6!
     pc = __builtin_fma(pc, z, 4.0587121264167685);  // pi^4/4!
     pc = __builtin_fma(pc, z, -4.934802200544679);  // -pi^2/2!
     const double cm1 = z * pc;
