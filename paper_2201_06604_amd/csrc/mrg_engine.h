@@ -385,14 +385,15 @@ __device__ __forceinline__ void sincospi_unit(double t, double* sp, double* cp) 
 }
 
 // log(u) for the generators' uniforms, u in [2^-33, 1), by table: u = m 2^k
-// with m in [1/2, 1); the top 8 fraction bits of m pick an interval of width
-// 1/512 whose entry holds R, a multiple of 2^-8 near 1/m (R = 1 on the last
-// interval), and -log(R) = hi + lo.  t = m R - 1 is exact (|t| < 2^-8, a
-// multiple of 2^-61), log(m) = -log(R) + log1p(t) with log1p(t) = t + t^2 P(t)
-// through t^7 (the next term, t^8/8, is below 2^-59 of t), and k ln2 + hi is
-// exact (hi a multiple of 2^-40, ln2_hi of 2^-32, |k| <= 33).  Near u = 1
-// (k = 0, R = 1) the result is log1p(t) alone, accurate relative to its own
-// size.
+// with m in [1/2, 1); the top 9 fraction bits of m pick an interval of width
+// 1/1024 whose entry holds R, a multiple of 2^-9 near 1/m (R = 1 on the last
+// interval), and -log(R) = hi + lo.  t = m R - 1 is exact (|t| < 2^-9, a
+// multiple of 2^-62), log(m) = -log(R) + log1p(t) with log1p(t) = t + t^2 P(t)
+// through t^6 (the next term, t^7/7, is below 2^-65: under 2^-55 of any
+// result outside the last interval, where |log u| >= 2^-10, and below 2^-54
+// of t on the last one), and k ln2 + hi is exact (hi a multiple of 2^-40,
+// ln2_hi of 2^-32, |k| <= 33).  Near u = 1 (k = 0, R = 1) the result is
+// log1p(t) alone, accurate relative to its own size.
 // SCALE (1, -1, 2 or -2) multiplies the result exactly.
 // mrg_transform_accuracy compares it with the HIP library's log over any
 // range of generator outputs.
@@ -401,12 +402,11 @@ __device__ __forceinline__ double log_unit(double u) {
     static_assert(SCALE == 1 || SCALE == -1 || SCALE == 2 || SCALE == -2, "power-of-two scale");
     const int k = __builtin_amdgcn_frexp_exp(u);
     const double m = __builtin_amdgcn_frexp_mant(u);  // [1/2, 1)
-    static_assert(kLogTabN == 256, "the index takes the top 8 fraction bits of m");
-    const uint32_t j = (static_cast<uint32_t>(__double2hiint(m)) >> 12) & (kLogTabN - 1);
+    static_assert(kLogTabN == 512, "the index takes the top 9 fraction bits of m");
+    const uint32_t j = (static_cast<uint32_t>(__double2hiint(m)) >> 11) & (kLogTabN - 1);
     const double* e = log_table_lds() + 3 * j;
     const double t = __builtin_fma(m, e[0], -1.0);
-    double p = 1.0 / 7.0;
-    p = __builtin_fma(p, t, -1.0 / 6.0);
+    double p = -1.0 / 6.0;
     p = __builtin_fma(p, t, 1.0 / 5.0);
     p = __builtin_fma(p, t, -1.0 / 4.0);
     p = __builtin_fma(p, t, 1.0 / 3.0);
