@@ -430,30 +430,24 @@ __device__ __forceinline__ double log_unit(double u) {
 // float is then under 4e-7 of max(|value|, 1), against the 1e-6 fp32
 // tolerance.
 
-// log(u) as log_unit, but s = f * rcp(d) with the hardware reciprocal alone
-// (relative error below 2^-23 on these divisors), and atanh(s) through s^7.
-// The truncation adds below 2|s| (s^2)^4 / 9 < 3e-8.  Near u = 1 (k = 0)
-// both errors are relative to log(u) itself, so the result keeps ~1e-7
-// relative accuracy where log(u) is tiny.
+// log(u) by log_unit's table (staged in LDS by the calling kernel): t = m R - 1
+// exact, |t| < 2^-9, and log1p(t) through t^3 (the next term, t^4/4 < 2^-38,
+// is below 2^-28 of any result outside the last interval, where
+// |log u| >= 2^-10, and below 2^-29 of t on the last one); -log R's low part
+// (below 2^-40) and the low bits of ln 2 are left out (below 2^-30 of the
+// result).  Near u = 1 (k = 0, R = 1) the result is log1p(t) alone, accurate
+// relative to its own size.
 template <int SCALE = 1>
 __device__ __forceinline__ double log_unit_f32out(double u) {
     static_assert(SCALE == 1 || SCALE == -1 || SCALE == 2 || SCALE == -2, "power-of-two scale");
-    int k = __builtin_amdgcn_frexp_exp(u);
-    double m = __builtin_amdgcn_frexp_mant(u);
-    const int lo = m < 0.70710678118654752440 ? 1 : 0;
-    m = __builtin_amdgcn_ldexp(m, lo);
-    k -= lo;
-    const double f = m - 1.0;
-    const double q = f * __builtin_amdgcn_rcp(2.0 + f);  // s = f / (2 + f)
-    const double z = q * q;
-    double r = 1.0 / 7.0;
-    r = __builtin_fma(r, z, 1.0 / 5.0);
-    r = __builtin_fma(r, z, 1.0 / 3.0);
-    r = r * z;
-    const double s2 = q * (2.0 * SCALE);
-    const double log_m = __builtin_fma(s2, r, s2);
+    const int k = __builtin_amdgcn_frexp_exp(u);
+    const double m = __builtin_amdgcn_frexp_mant(u);  // [1/2, 1)
+    const uint32_t j = (static_cast<uint32_t>(__double2hiint(m)) >> 11) & (kLogTabN - 1);
+    const double* e = log_table_lds() + 3 * j;
+    const double t = __builtin_fma(m, e[0], -1.0);
+    const double q = (t * t) * __builtin_fma(t, 1.0 / 3.0, -0.5);
     constexpr double kLn2 = 6.93147180559945286227e-01;
-    return __builtin_fma(static_cast<double>(k), kLn2 * SCALE, log_m);
+    return (__builtin_fma(static_cast<double>(k), kLn2, e[1]) + (t + q)) * SCALE;
 }
 
 // sqrt(x) for the radius argument, x in [2^-32, 47]: the hardware reciprocal
@@ -466,32 +460,23 @@ __device__ __forceinline__ double sqrt_radius_f32out(double x) {
     return __builtin_fma(d, 0.5 * y, g);
 }
 
-// sin(pi t), cos(pi t) as sincospi_unit, with the Taylor series cut at r^9
-// (sine) and r^10 (cosine): at |r| = 1/4 the next terms are below 2e-9 and
-// 2e-10.
+// sin(pi t), cos(pi t) by sincospi_unit's table (staged in LDS by the calling
+// kernel, the high parts only): d = t - j/64, |d| <= 1/128, sin(pi d) through
+// d^3 (next term below 3e-9 of it) and cos(pi d) - 1 through d^2 (next term
+// below 1.5e-8 in absolute value; beside the zero of cos(pi t) it is scaled
+// by |c_j| <= 0.05, under 4e-8 of the result there).  On the axes the table
+// holds exact zeros and ones, so results near the zeros of sin and cos keep
+// their relative accuracy.
 __device__ __forceinline__ void sincospi_unit_f32out(double t, double* sp, double* cp) {
-    const double n = __builtin_rint(t + t);
-    const double r = __builtin_fma(n, -0.5, t);
-    const double z = r * r;
-    double ps = 0.08214588661112823;
-    ps = __builtin_fma(ps, z, -0.5992645293207921);
-    ps = __builtin_fma(ps, z, 2.5501640398773455);
-    ps = __builtin_fma(ps, z, -5.16771278004997);
-    ps = __builtin_fma(ps, z, 3.141592653589793);
-    const double sn = r * ps;
-    double pc = -0.02580689139001406;
-    pc = __builtin_fma(pc, z, 0.2353306303588932);
-    pc = __builtin_fma(pc, z, -1.3352627688545895);
-    pc = __builtin_fma(pc, z, 4.0587121264167685);
-    pc = __builtin_fma(pc, z, -4.934802200544679);
-    const double cs = __builtin_fma(pc, z, 1.0);
-    const uint32_t ni = static_cast<uint32_t>(static_cast<int>(n));
-    const double s1 = (ni & 1u) ? cs : sn;
-    const double c1 = (ni & 1u) ? sn : cs;
-    const uint32_t sgn_s = (ni << 30) & 0x80000000u;
-    const uint32_t sgn_c = ((ni + 1u) << 30) & 0x80000000u;
-    *sp = __hiloint2double(__double2hiint(s1) ^ static_cast<int>(sgn_s), __double2loint(s1));
-    *cp = __hiloint2double(__double2hiint(c1) ^ static_cast<int>(sgn_c), __double2loint(c1));
+    const double jd = __builtin_rint(t * 64.0);
+    const double d = __builtin_fma(jd, -1.0 / 64.0, t);
+    const double* e = sincos_table_lds() + 4 * static_cast<int>(jd);
+    const double z = d * d;
+    const double sd = d * __builtin_fma(z, -5.16771278004997, 3.141592653589793);  // pi d - (pi d)^3/6
+    const double cm1 = z * -4.934802200544679;                                     // -(pi d)^2/2
+    const double sh = e[0], ch = e[2];
+    *sp = __builtin_fma(ch, sd, __builtin_fma(sh, cm1, sh));
+    *cp = __builtin_fma(-sh, sd, __builtin_fma(ch, cm1, ch));
 }
 
 __device__ __forceinline__ double to_f64(uint32_t z) { return static_cast<double>(z); }

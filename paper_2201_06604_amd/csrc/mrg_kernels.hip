@@ -412,7 +412,7 @@ __device__ __forceinline__ void run_chunk(const GenLaunch& L, uint32_t sblk, uin
 // ending their wave (a wave's lane 0 always holds a stream).
 template <int DIST, int DTYPE, int ARITH, int SPL, bool NT, bool LOCK>
 __global__ void __launch_bounds__(1024) gen_kernel(GenLaunch L) {
-    if constexpr ((DIST == kNormal || DIST == kExponential) && DTYPE == kF64) stage_tables();
+    if constexpr (DIST == kNormal || DIST == kExponential) stage_tables();
     // Block -> (stream block, chunk).  With xcd remapping, consecutive logical
     // blocks (neighbouring row segments) land on one XCD, whose L2 then sees
     // contiguous runs of every row; blocks are dealt to the 8 XCDs in turn.
@@ -1325,7 +1325,7 @@ __host__ __device__ inline uint64_t paper_lanes_per_chunk(const PaperLaunch& L) 
 
 template <int DIST, int DTYPE, int G>
 __global__ void __launch_bounds__(256) paper_kernel(PaperLaunch L) {
-    if constexpr ((DIST == kNormal || DIST == kExponential) && DTYPE == kF64) stage_tables();
+    if constexpr (DIST == kNormal || DIST == kExponential) stage_tables();
     using Engine = typename EngineOf<G>::T;
     using T = typename ElemOf<DTYPE>::T;
     const uint64_t id = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
