@@ -148,14 +148,14 @@ def test_generate_plan_resolves_the_launch():
         assert p["lockstep"] == 0 and p["nontemporal"] == 1, (dist, dtype, p)
         units = 4096 // 2 if dist == P.MRG_NORMAL else 4096
         assert p["chunk"] * -(-units // p["chunk"]) >= units
-    # grids that fill the chip keep lockstep at ragged stream counts (idle
-    # waves pass the barriers); small, latency-bound grids run free
-    for S2, n2 in [(100000, 10 ** 8), (300000, 300000 * 4096 + 17), (131072, 131072 * 4096)]:
+    # full-size calls (2^29 draws and up) keep lockstep at ragged stream
+    # counts (idle waves pass the barriers); small, latency-bound grids run free
+    for S2, n2 in [(100000, 10 ** 9), (300000, 300000 * 4096 + 17), (131072, 131072 * 4096)]:
         p = P.mrg_generate_plan(S2, n2)
         assert p["lockstep"] == 1 and p["block"] == 512 and S2 % p["streams_per_lane"] == 0, (S2, p)
     for S2, n2 in [(1024, 1024 * 1024), (1000, 1000 * 37 + 5), (1, 1001)]:
         p = P.mrg_generate_plan(S2, n2)
-        assert p["lockstep"] == 0 and p["block"] == 256, (S2, p)
+        assert p["lockstep"] == 0, (S2, p)
     cfg = dict(block=1024, chunk=7, streams_per_lane=4, lockstep=1, nontemporal=0, xcd_remap=0, arith=1)
     assert P.mrg_generate_plan(1000, 50000, P.MRG_UNIFORM, P.MRG_F32, cfg=cfg) == cfg
     assert P.mrg_generate_plan(S, n, gen=P.MRG_GEN_MRG31K3P)["arith"] == 0

@@ -152,14 +152,16 @@ def test_lockstep_blocks(cfg, dist, dtype, S, n):
 
 @pytest.mark.parametrize("S,n", [(100003, 100003 * 700 + 77), (100000, 100000 * 700 + 99999), (65536, 65536 * 1100)])
 def test_default_plan_lockstep_at_scale(S, n):
-    """Automatic launches large enough for lockstep blocks: ragged stream
-    counts (the last block's spare waves only pass the barriers), odd S (one
-    stream per lane, rows off 128-byte lines, ordinary stores) and a ragged
-    tail; every value and state against the oracle."""
-    plan = P.mrg_generate_plan(S, n)
+    """The automatic full-size shape (lockstep blocks) at these stream counts,
+    over fewer draws per stream: ragged stream counts (the last block's spare
+    waves only pass the barriers), odd S (one stream per lane, rows off
+    128-byte lines, ordinary stores) and a ragged tail; every value and state
+    against the oracle."""
+    plan = P.mrg_generate_plan(S, 1 << 30)
     assert plan["lockstep"] == 1, plan
+    cfg = {k: v for k, v in plan.items() if k != "chunk"}
     rec = O.create_streams(GEN, workloads.random_seed(S), S)
-    run_case(rec, n, P.MRG_UNIFORM, P.MRG_F64)
+    run_case(rec, n, P.MRG_UNIFORM, P.MRG_F64, 1.0, cfg)
 
 
 @pytest.mark.parametrize("rate", [0.5, 3.0])

@@ -141,10 +141,13 @@ def test_launch_shapes(cfg):
 
 @pytest.mark.parametrize("S,n", [(65536, 65536 * 1100), (100003, 100003 * 700 + 77)])
 def test_default_plan_lockstep_at_scale(S, n):
-    """fp64 uniforms at sizes where the automatic plan runs lockstep blocks
-    (several chunks per stream; an odd stream count with spare waves)."""
-    assert P.mrg_generate_plan(S, n, gen=G)["lockstep"] == 1
-    run(records(workloads.random_seed(S) % np.uint32(P2), S), n, P.MRG_UNIFORM, P.MRG_F64)
+    """fp64 uniforms in the automatic full-size shape (lockstep blocks) at
+    these stream counts (several chunks per stream; an odd stream count with
+    spare waves)."""
+    plan = P.mrg_generate_plan(S, 1 << 30, gen=G)
+    assert plan["lockstep"] == 1, plan
+    cfg = {k: v for k, v in plan.items() if k != "chunk"}
+    run(records(workloads.random_seed(S) % np.uint32(P2), S), n, P.MRG_UNIFORM, P.MRG_F64, cfg=cfg)
 
 
 def test_extreme_states():
