@@ -40,9 +40,19 @@ VALU_PEAK_LANE_INSTR = 256 * 4 * 16 * 2.4e9
 # the algorithmic work of a draw, so that a kernel that does the same work in
 # fewer instructions shows as a higher fraction rather than a smaller model;
 # issued_frac (the kernel's own measured instructions over the same time and
-# ceiling) is reported beside it
+# ceiling) is reported beside it.  The fp32 normals and exponentials changed
+# method (fp32 series on the fp64 tables instead of the fp64 transform rounded),
+# so theirs are the new kernels' counts: VALU instructions of the main loop of
+# the gfx950 assembly over the draws one iteration stores (the same count gives
+# 18.17 for fp64 uniforms, measured 18.18, and 19.17 for fp32 uniforms,
+# measured 19.29)
 OPS_PER_DRAW = {"f64_uniform": 18.2, "f32_uniform": 19.6, "f64_normal": 54.9, "f64_exponential": 48.3,
-                "f32_normal": 54.9, "f32_exponential": 48.3}
+                "f32_normal": 36.1, "f32_exponential": 32.2}
+# The same for the contingency-table kernels: lane-instructions per table of
+# the 10^6-table mix and per Fisher replicate of the 7 x 12 table, counted with
+# SQ_INSTS_VALU on the tables kernel with 6 checkpoints and the Fisher kernel
+# with 8 (their inversion loops' trip counts depend on the margins), frozen
+OPS_PER_TABLE = {"tables_kernel": 43136.9, "fisher_kernel": 692654.1}
 VALU_JSON = os.path.join(ROOT, "profiles", "gen_kernels_valu_262144x4096.json")
 
 
@@ -543,13 +553,14 @@ def bench_tables(torch, P, workloads, reps=10, with_oracle=True):
            "ms": round(ms, 3), "Mtables_per_s": round(n / ms / 1e3, 1),
            "GUniforms_per_s": round(draws / ms / 1e6, 2)}
     vp = valu_profile()
-    if vp and "tables_kernel" in vp.get("per_unit", {}):
-        res["roofline"] = alu_roofline(vp["per_unit"]["tables_kernel"], n, ms)
-        res["roofline"]["kernel"] = "tables_kernel"
+    meas = vp["per_unit"].get("tables_kernel") if vp else None
+    res["roofline"] = alu_roofline(OPS_PER_TABLE["tables_kernel"], n, ms, meas)
+    res["roofline"]["kernel"] = "tables_kernel"
+    if meas is not None:
         res["roofline"]["valu_busy_profiled"] = vp.get("valu_busy", {}).get("tables_kernel")
-        res["roofline"]["note"] = ("ops_per_unit = issued VALU lane-slots per table (wave-instructions x 64, "
-                                   "SQ_INSTS_VALU): the inversion loops' trip counts depend on the margins, and "
-                                   "a wave issues until its longest lane is done")
+    res["roofline"]["note"] = ("ops_per_unit = issued VALU lane-slots per table (wave-instructions x 64, "
+                               "SQ_INSTS_VALU, frozen): the inversion loops' trip counts depend on the "
+                               "margins, and a wave issues until its longest lane is done")
     del d, tabs, stats
     if with_oracle:
         res["oracle"] = tables_oracle_sample(I, J, rows, cols, workloads.random_seed())
@@ -570,10 +581,12 @@ def bench_tables(torch, P, workloads, reps=10, with_oracle=True):
             "table": f"{tab.shape[0]}x{tab.shape[1]}", "B": B, "ms": round(ms, 2),
             "Mtables_per_s": round(B / ms / 1e3, 2), "pvalue": round(P.mrg_fisher_pvalue(int(cnt.item()), B), 6),
             "paper_V100_s": paper_s}
-        if key == "week" and vp and "fisher_kernel" in vp.get("per_unit", {}):
-            fis[key]["roofline"] = alu_roofline(vp["per_unit"]["fisher_kernel"], B, ms)
+        if key == "week":
+            meas = vp["per_unit"].get("fisher_kernel") if vp else None
+            fis[key]["roofline"] = alu_roofline(OPS_PER_TABLE["fisher_kernel"], B, ms, meas)
             fis[key]["roofline"]["kernel"] = "fisher_kernel"
-            fis[key]["roofline"]["valu_busy_profiled"] = vp.get("valu_busy", {}).get("fisher_kernel")
+            if meas is not None:
+                fis[key]["roofline"]["valu_busy_profiled"] = vp.get("valu_busy", {}).get("fisher_kernel")
         del d
     res["fisher"] = fis
     if with_oracle:
