@@ -74,9 +74,10 @@ __device__ __forceinline__ void dev_jump(uint32_t x[6], uint64_t e) {
         if (e & 1) dev_apply<G>(dev_tab<G>().step_pow2[0][b], dev_tab<G>().step_pow2[1][b], x);
 }
 
-// x <- A^e x by base-64 digits of e (wave-uniform): one exact fp64
-// matrix-vector product per nonzero digit instead of one integer product per
-// set bit.  x canonical in and out.
+// x <- A^e x by base-64 digits of e: one exact fp64 matrix-vector product per
+// nonzero digit instead of one integer product per set bit.  x canonical in
+// and out.  Any e < 2^64 (the tables hold 11 digits); a wave-uniform e keeps
+// the table reads scalar.
 template <int G = kGen32k3a>
 __device__ __forceinline__ void dev_jump_digits(uint32_t x[6], uint64_t e) {
     const StepDigitsF64& T = G == kGen32k3a ? g_stepdig : g_stepdig31;
@@ -454,8 +455,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(uint32_t* streams, uint32
     uint32_t x[6];
 #pragma unroll
     for (int w = 0; w < 6; ++w) x[w] = rec[w];
-    for (int b = 0; b < 64; ++b)  // uniform loop: table loads stay scalar
-        if ((steps >> b) & 1) dev_apply<G>(dev_tab<G>().step_pow2[0][b], dev_tab<G>().step_pow2[1][b], x);
+    dev_jump_digits<G>(x, steps);  // lanes hold one or two distinct counts
 #pragma unroll
     for (int w = 0; w < 6; ++w) rec[w] = x[w];
 }
@@ -817,8 +817,7 @@ __global__ void __launch_bounds__(256) batch_finalize_kernel(BatchLaunch B) {
     uint32_t x[6];
 #pragma unroll
     for (int w = 0; w < 6; ++w) x[w] = rec[w];
-    for (int b = 0; b < 64; ++b)
-        if ((steps >> b) & 1) dev_apply<kGen32k3a>(g_tab.step_pow2[0][b], g_tab.step_pow2[1][b], x);
+    dev_jump_digits<kGen32k3a>(x, steps);
 #pragma unroll
     for (int w = 0; w < 6; ++w) rec[w] = x[w];
 }
@@ -1415,8 +1414,7 @@ __global__ void __launch_bounds__(256) paper_finalize_kernel(PaperLaunch L) {
         uint32_t x[6];
 #pragma unroll
         for (int w = 0; w < 6; ++w) x[w] = rec[w];
-        for (int b = 0; b < 64; ++b)
-            if ((visits >> b) & 1) dev_apply<G>(dev_tab<G>().step_pow2[0][b], dev_tab<G>().step_pow2[1][b], x);
+        dev_jump_digits<G>(x, visits);
 #pragma unroll
         for (int w = 0; w < 6; ++w) rec[w] = x[w];
     }
