@@ -941,7 +941,7 @@ __global__ void __launch_bounds__(256) advance_kernel(uint32_t* streams, uint64_
     uint32_t x[6];
 #pragma unroll
     for (int w = 0; w < 6; ++w) x[w] = rec[w];
-    dev_jump<G>(x, steps);
+    dev_jump_digits<G>(x, steps);
 #pragma unroll
     for (int w = 0; w < 6; ++w) rec[w] = x[w];
 }

@@ -273,6 +273,24 @@ def test_substreams_and_advance():
     torch.cuda.synchronize()
     np.testing.assert_array_equal(P.as_u32(d), work)
 
+# Counts whose base-64 digits are 1 and 63 at every position, the largest
+# count, and a mixed one: the device jump takes one table product per digit.
+ADVANCE_COUNTS = [c for d in range(11) for v in (1, 63) for c in [v << (6 * d)] if c < 2**64] + \
+    [2**64 - 1, 0x0123456789ABCDEF, 3]
+
+
+def test_advance_every_digit():
+    """Each advance against the oracle's, state by state."""
+    rec = O.create_streams(GEN, workloads.random_seed(13), 67)
+    d = dev_streams(rec)
+    work = rec.copy()
+    for c in ADVANCE_COUNTS:
+        P.mrg_streams_advance(d, c)
+        O.advance(GEN, work, c)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(P.as_u32(d), work, err_msg=f"count {c:#x}")
+
+
 
 def test_export_import_roundtrip_continues_identically():
     """Save/restore (saveRDS/readRDS example): generation continued from a

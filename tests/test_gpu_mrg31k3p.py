@@ -194,6 +194,24 @@ def test_substreams_and_advance():
     np.testing.assert_array_equal(P.as_u32(d), work)
 
 
+# as in the MRG32k3a tests: base-64 digits 1 and 63 at every position
+ADVANCE_COUNTS = [c for d in range(11) for v in (1, 63) for c in [v << (6 * d)] if c < 2**64] + \
+    [2**64 - 1, 0x0123456789ABCDEF, 3]
+
+
+def test_advance_every_digit():
+    """Each advance against the oracle's, state by state."""
+    rec = records(workloads.random_seed(13) % np.uint32(P2), 67)
+    d = dev(rec)
+    work = rec.copy()
+    for c in ADVANCE_COUNTS:
+        P.mrg_streams_advance(d, c, gen=G)
+        O.advance(GEN, work, c)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(P.as_u32(d), work, err_msg=f"count {c:#x}")
+
+
+
 def test_export_import_roundtrip():
     c = P.mrg_creator_init(workloads.PAPER_SEED, gen=G)
     d = P.mrg_streams_create_device(c, 300, gen=G)
