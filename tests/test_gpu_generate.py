@@ -337,18 +337,20 @@ def test_reproducible_by_creation_order():
 
 
 # ------------------------------------------------------------ full size
-FULL_VARIANTS = [(P.MRG_UNIFORM, P.MRG_F64), (P.MRG_UNIFORM, P.MRG_F32), (P.MRG_NORMAL, P.MRG_F64),
-                 (P.MRG_EXPONENTIAL, P.MRG_F64)]
+FULL_VARIANTS = [(P.MRG_UNIFORM, P.MRG_F64), (P.MRG_UNIFORM, P.MRG_F32), (P.MRG_RAW, P.MRG_U32),
+                 (P.MRG_NORMAL, P.MRG_F64), (P.MRG_EXPONENTIAL, P.MRG_F64), (P.MRG_NORMAL, P.MRG_F32),
+                 (P.MRG_EXPONENTIAL, P.MRG_F32)]
 
 
+@pytest.mark.parametrize("S", [262144, 65536])
 @pytest.mark.parametrize("dist,dtype", FULL_VARIANTS, ids=lambda v: str(v))
-def test_throughput_config_full_size_sampled(dist, dtype):
-    """262,144 streams x 4,096 draws (2^30) of every variant the benchmark
-    times (fp64 and fp32 uniforms, fp64 normals, fp64 exponentials), in the
-    launch shape it times: every final state, 4,096 random streams in full,
-    and the first 16 draws of every stream (uniforms bit-exact, transforms
-    within the tolerance)."""
-    S, per = 262144, 4096
+def test_throughput_config_full_size_sampled(dist, dtype, S):
+    """S streams x 4,096 draws of every output kind in the automatic launch
+    shape: 2^30 draws (the shapes the benchmark times) and 2^28 (the next
+    size class's tuned shapes).  Every final state, 4,096 random streams in
+    full, and the first 16 draws of every stream (uniforms and raw words
+    bit-exact, transforms within the tolerance)."""
+    per = 4096
     seed = workloads.random_seed()
     c = P.mrg_creator_init(seed)
     d = P.mrg_streams_create_device(c, S)
@@ -363,12 +365,13 @@ def test_throughput_config_full_size_sampled(dist, dtype):
     np.testing.assert_array_equal(P.as_u32(d)[:, 0:6], fin)
     np.testing.assert_array_equal(P.as_u32(d)[:, 6:18], rec[:, 6:18])
     mat = out.view(per, S)
-    head = mat[:16].cpu().numpy()
+    u32 = (lambda a: a.view(np.uint32)) if dtype == P.MRG_U32 else (lambda a: a)
+    head = u32(mat[:16].cpu().numpy())
     want_head = O.generate(GEN, rec.copy(), 16 * S, ODIST[dist], ODT[dtype], threads=8).reshape(16, S)
     check_values(head.ravel(), want_head.ravel(), dist, dtype, ctx="first 16 draws of every stream")
     rnd = np.random.default_rng(3)
     idx = np.sort(rnd.choice(S, size=4096, replace=False))
-    cols = mat[:, torch.from_numpy(idx).cuda()].cpu().numpy()
+    cols = u32(mat[:, torch.from_numpy(idx).cuda()].cpu().numpy())
     sub = rec[idx].copy()
     want_cols = O.generate(GEN, sub, per * 4096, ODIST[dist], ODT[dtype], threads=8).reshape(per, 4096)
     check_values(cols.ravel(), want_cols.ravel(), dist, dtype, ctx="4096 whole streams")
