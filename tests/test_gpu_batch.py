@@ -168,6 +168,55 @@ def test_batch_relaunch_continues_streams():
         assert torch.equal(A.streams[i], B.streams[i])
 
 
+# Requests whose last stream block is small (1, 16, 20, 32 or 36 streams of
+# 64), a normal request with an odd count, a single stream: over gangs, tiny
+# and odd chunks and a single chunk.
+SMALL_TAIL_MIX = [
+    (65, 65 * 400 + 3, P.MRG_UNIFORM, P.MRG_F64, 1.0),
+    (96, 96 * 300 + 50, P.MRG_NORMAL, P.MRG_F64, 1.0),
+    (100, 100 * 257, P.MRG_NORMAL, P.MRG_F32, 1.0),
+    (80, 80 * 513 + 79, P.MRG_EXPONENTIAL, P.MRG_F32, 0.5),
+    (20, 20 * 700, P.MRG_RAW, P.MRG_U32, 1.0),
+    (1, 5000, P.MRG_UNIFORM, P.MRG_F32, 1.0),
+    (130, 130 * 1001 + 7, P.MRG_EXPONENTIAL, P.MRG_F64, 1.0),
+    (40, 40 * 301, P.MRG_NORMAL, P.MRG_F64, 1.0),
+    (144, 144 * 222 + 100, P.MRG_UNIFORM, P.MRG_F64, 1.0),
+]
+
+
+@pytest.mark.parametrize("cfg", [dict(gang_waves=8, tile_units=64, wide_stores=1),
+                                 dict(gang_waves=4, tile_units=200, waves_per_simd=2, wide_stores=1),
+                                 dict(gang_waves=8, wide_stores=2),
+                                 dict(gang_waves=2, tile_units=6, wide_stores=1),
+                                 dict(gang_waves=8, tile_units=2, wide_stores=1),
+                                 dict(gang_waves=4, tile_units=63, wide_stores=1),
+                                 dict(gang_waves=4, tile_units=100000, wide_stores=1),
+                                 None], ids=str)
+def test_batch_small_last_blocks(cfg):
+    """The plain launch's values and states, and the oracle's."""
+    A, B = Mix(SMALL_TAIL_MIX, 2), Mix(SMALL_TAIL_MIX, 2)
+    plan = P.BatchPlan(A.requests(), cfg)
+    plan.upload()
+    plan.launch()
+    want = B.plain()
+    torch.cuda.synchronize()
+    for i, (S, n, dist, dtype, rate) in enumerate(SMALL_TAIL_MIX):
+        assert _equal(A.outs[i], want[i], n), f"request {i} cfg {cfg}"
+        assert torch.equal(A.streams[i], B.streams[i]), f"states {i} cfg {cfg}"
+        work = A.host_rec[i].copy()
+        ref = O.generate(GEN, work, n, ODIST[dist], ODT[dtype], rate)
+        got = A.outs[i].cpu().numpy()[:n]
+        if dtype == P.MRG_U32:
+            got = got.view(np.uint32)
+        if dist in (P.MRG_UNIFORM, P.MRG_RAW):
+            assert np.array_equal(got, ref), f"request {i} cfg {cfg}"
+        else:
+            tol = 1e-15 if dtype == P.MRG_F64 else 1e-6
+            err = np.abs(got.astype(np.float64) - ref) / np.maximum(np.abs(ref), 1.0)
+            assert err.max() <= tol, f"request {i} cfg {cfg}: {err.max()}"
+        np.testing.assert_array_equal(P.as_u32(A.streams[i]), work)
+
+
 @pytest.mark.parametrize("cfg", [dict(tile_units=200, gang_waves=1), dict(tile_units=200, gang_waves=4),
                                  dict(tile_units=200, gang_waves=4, wide_stores=2, waves_per_simd=6)], ids=str)
 def test_batch_graph_replay_matches_eager(cfg):
