@@ -378,22 +378,28 @@ def test_throughput_config_full_size_sampled(dist, dtype, S):
     del out
 
 
-def test_throughput_config_every_number():
-    """All 2^30 fp64 uniforms of the throughput configuration, in the launch
-    the benchmark times, compared with the oracle in blocks of 16,384 streams
-    (columns of the k*S + s layout; about 4 s with 16 host threads)."""
+@pytest.mark.parametrize("dist,dtype", FULL_VARIANTS, ids=lambda v: str(v))
+def test_throughput_config_every_number(dist, dtype):
+    """All 2^30 numbers of the throughput configuration, for every output kind
+    the benchmark times, in the launch it times, compared with the oracle in
+    blocks of 16,384 streams (columns of the k*S + s layout): uniforms and raw
+    words bit-exact, transforms within the tolerance (1-8 s per kind with 16
+    host threads)."""
     S, per, blk = 262144, 4096, 16384
     seed = workloads.random_seed()
     c = P.mrg_creator_init(seed)
     d = P.mrg_streams_create_device(c, S)
     rec = O.create_streams(GEN, seed.copy(), S)
-    out = P.mrg_generate(d, S * per, P.MRG_UNIFORM, P.MRG_F64)
+    out = P.mrg_generate(d, S * per, dist, dtype)
     torch.cuda.synchronize()
     mat = out.view(per, S)
     for s0 in range(0, S, blk):
         got = mat[:, s0:s0 + blk].cpu().numpy()
-        want = O.generate(GEN, rec[s0:s0 + blk].copy(), per * blk, threads=16).reshape(per, blk)
-        assert np.array_equal(got, want), f"streams {s0}..{s0 + blk - 1}"
+        if dtype == P.MRG_U32:
+            got = got.view(np.uint32)
+        want = O.generate(GEN, rec[s0:s0 + blk].copy(), per * blk, ODIST[dist], ODT[dtype],
+                          threads=16).reshape(per, blk)
+        check_values(got.ravel(), want.ravel(), dist, dtype, ctx=f"streams {s0}..{s0 + blk - 1}")
     del out
 
 
