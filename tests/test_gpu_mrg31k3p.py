@@ -249,3 +249,27 @@ def test_tables_and_fisher_with_mrg31k3p():
     cnt, _, _ = P.mrg_fisher_sim(d, tab, gen=G)
     wcnt, _ = O.fisher_count(GEN, rec.copy(), tab)
     assert int(cnt.item()) == wcnt
+
+
+def test_throughput_size_every_number():
+    """The benchmarked MRG31k3p launch: 262,144 streams created on the device
+    from the paper's seed, 4,096 fp64 uniforms each in the automatic shape;
+    all 2^30 numbers bit-exact against the oracle in blocks of 16,384 streams,
+    and every final state."""
+    S, per, blk = 262144, 4096, 16384
+    c = P.mrg_creator_init(workloads.PAPER_SEED, gen=G)
+    d = P.mrg_streams_create_device(c, S, gen=G)
+    rec = O.create_streams(GEN, np.array(workloads.PAPER_SEED, dtype=np.uint32), S)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(P.as_u32(d), rec)
+    out = P.mrg_generate(d, S * per, P.MRG_UNIFORM, P.MRG_F64, gen=G)
+    torch.cuda.synchronize()
+    fin = rec[:, 0:6].copy()
+    O.jump_many(GEN, fin, per)
+    np.testing.assert_array_equal(P.as_u32(d)[:, 0:6], fin)
+    mat = out.view(per, S)
+    for s0 in range(0, S, blk):
+        got = mat[:, s0:s0 + blk].cpu().numpy()
+        want = O.generate(GEN, rec[s0:s0 + blk].copy(), per * blk, O.UNIFORM, O.F64, threads=16).reshape(per, blk)
+        assert np.array_equal(got, want), f"streams {s0}..{s0 + blk - 1}"
+    del out
