@@ -155,3 +155,23 @@ def test_paper_rnorm_example_sampled():
             st = rec[s, :6].copy()
             O.jump(O.MRG31K3P, st, k)
             np.testing.assert_array_equal(after[s, :6], st)
+
+
+def test_paper_rnorm_example_every_number():
+    """Section 3.1's rnormGpu(c(10000, 10000)) on a 512 x 128 lattice of
+    65,536 MRG31k3p streams: all 10^8 normals against the oracle's
+    paper-geometry generator, within 1e-15, and every stream record after."""
+    gen = P.MRG_GEN_MRG31K3P
+    n_s, G0, G1, N = 65536, 512, 128, 10000
+    c = P.mrg_creator_init(workloads.PAPER_SEED, gen=gen)
+    d = P.mrg_streams_create_device(c, n_s, gen=gen)
+    work = P.as_u32(d).copy()
+    out = P.mrg_generate_paper(d, N, N, G0, G1, P.MRG_NORMAL, gen=gen)
+    torch.cuda.synchronize()
+    want = O.generate_paper(O.MRG31K3P, work, N, N, G0, G1, O.NORMAL, O.F64)
+    for r0 in range(0, N, 1000):
+        got = out[r0:r0 + 1000].cpu().numpy()
+        w = want[r0:r0 + 1000]
+        err = np.abs(got - w) / np.maximum(np.abs(w), 1.0)
+        assert err.max() <= 1e-15, (r0, err.max())
+    np.testing.assert_array_equal(P.as_u32(d), work)
