@@ -327,3 +327,41 @@ def test_batched_config_full_size(cfg):
         else:
             tol = 1e-15 if dtype == P.MRG_F64 else 1e-6
             assert (np.abs(got.astype(np.float64) - ref) / np.maximum(np.abs(ref), 1.0)).max() <= tol
+
+
+def test_batched_config_every_number():
+    """The 4,096-request mix in the default plan: every number of every
+    request (4.4e9 in all; uniforms bit-exact, transforms within 1e-15 fp64 /
+    1e-6 fp32) and every stream record against the oracle."""
+    reqs = workloads.batch_requests()
+    total_S = sum(r["n_streams"] for r in reqs)
+    seed = workloads.random_seed(5)
+    c = P.mrg_creator_init(seed)
+    allA = P.mrg_streams_create_device(c, total_S)
+    dmap = {0: P.MRG_UNIFORM, 1: P.MRG_NORMAL, 2: P.MRG_EXPONENTIAL}
+    tmap = {0: P.MRG_F64, 1: P.MRG_F32}
+    creqs, outs, meta = [], [], []
+    for r in reqs:
+        dist, dtype = dmap[r["dist"]], tmap[r["dtype"]]
+        sA = allA[r["first_stream"]:r["first_stream"] + r["n_streams"]]
+        o = torch.empty(r["n"], dtype=TDT[dtype], device="cuda")
+        outs.append(o)
+        creqs.append(P.make_request(sA, r["n"], dist, dtype, 1.0, o))
+        meta.append((r, dist, dtype))
+    plan = P.BatchPlan(creqs)
+    plan.upload()
+    plan.launch()
+    torch.cuda.synchronize()
+    rec = O.create_streams(GEN, seed.copy(), total_S)
+    for i, (r, dist, dtype) in enumerate(meta):
+        sub = rec[r["first_stream"]:r["first_stream"] + r["n_streams"]]
+        want = O.generate(GEN, sub, r["n"], ODIST[dist], ODT[dtype], 1.0, threads=16)
+        got = outs[i].cpu().numpy()
+        if dist == P.MRG_UNIFORM:
+            assert np.array_equal(got, want), f"request {i}"
+        else:
+            tol = 1e-15 if dtype == P.MRG_F64 else 1e-6
+            err = np.abs(got.astype(np.float64) - want) / np.maximum(np.abs(want), 1.0)
+            assert err.max() <= tol, f"request {i}: {err.max()}"
+        outs[i] = None
+    np.testing.assert_array_equal(P.as_u32(allA), rec)
