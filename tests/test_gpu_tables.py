@@ -194,6 +194,26 @@ def test_fisher_count_matches_oracle(name, B):
         assert got[b] == want, b
 
 
+def test_fisher_month_full_size_count():
+    """Table 1 (12 x 12) at the benchmarked B = 2^20: the count equals the
+    oracle's (its replicates split over 16 host threads) and every stream
+    advances as the oracle's does."""
+    from concurrent.futures import ThreadPoolExecutor
+    tab = _golden_table("fisher_month.txt")
+    B = 1 << 20
+    rec = _records(workloads.random_seed(43), B)
+    d = _device(rec.view(np.int32).copy())
+    cnt, obs, _ = P.mrg_fisher_sim(d, tab)
+    torch.cuda.synchronize()
+    work = rec.copy()
+    bounds = np.linspace(0, B, 17).astype(int)
+    with ThreadPoolExecutor(16) as ex:
+        parts = list(ex.map(lambda k: O.fisher_count(GEN, work[bounds[k]:bounds[k + 1]], tab), range(16)))
+    assert int(cnt.item()) == sum(p[0] for p in parts)
+    assert obs == parts[0][1]
+    np.testing.assert_array_equal(d.cpu().numpy().view(np.uint32), work)
+
+
 def test_fisher_edge_cases():
     rec = _records(workloads.random_seed(42), 300)
     d = _device(rec.view(np.int32).copy())
