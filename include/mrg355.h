@@ -417,9 +417,9 @@ mrg_status mrg_batch_launch_static(const mrg_batch_plan* plan, hipStream_t strea
 mrg_status mrg_batch_request_times(const mrg_batch_plan* plan, const void* dev_workspace,
                                    uint64_t* host_ticks, hipStream_t stream);
 
-/* Autotuner: time candidate shapes (tile_units in {256, ..., 8192} x
- * gang_waves in {1, 4, 8} x wide_stores in {1, 2} x waves_per_simd in
- * {2, 3, 4, 6}; a waves setting that the kernel's registers cap to the grid of
+/* Autotuner: time candidate shapes (tile_units in {192, 256, 512, ..., 8192}
+ * x gang_waves in {1, 4, 8} x wide_stores in {1, 2} x waves_per_simd in
+ * {2, 3, 4, 5, 6}; a waves setting that the kernel's registers cap to the grid of
  * the one before is skipped) of the plan on the GPU with its own requests,
  * in `dev_workspace` (capacity `workspace_bytes`; shapes whose workspace would
  * not fit are skipped: mrg_batch_autotune_workspace_size gives the capacity

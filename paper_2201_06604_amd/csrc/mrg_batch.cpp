@@ -539,10 +539,10 @@ mrg_status mrg_batch_workspace_size(const mrg_batch_plan* plan, size_t* bytes) {
 // lane (widest stores a request allows, or one stream per lane) x waves per
 // SIMD.  Tile length sets the per-stream work-item count (a stream of u units
 // is cut into ceil(u / tile_units) work-items).
-static constexpr uint32_t kTuneTileUnits[] = {256, 512, 1024, 2048, 4096, 8192};
+static constexpr uint32_t kTuneTileUnits[] = {192, 256, 512, 1024, 2048, 4096, 8192};
 static constexpr uint32_t kTuneGang[] = {1, 4, 8};
 static constexpr uint32_t kTuneWide[] = {1, 2};
-static constexpr uint32_t kTuneWaves[] = {2, 3, 4, 6};
+static constexpr uint32_t kTuneWaves[] = {2, 3, 4, 5, 6};
 
 mrg_status mrg_batch_autotune_workspace_size(const mrg_batch_plan* plan, size_t* bytes) {
     if (!plan || !bytes) return mrg355_fail(MRG_E_INVALID_ARG, "NULL plan or bytes");
