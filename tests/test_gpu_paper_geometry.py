@@ -98,8 +98,6 @@ def test_geometry_matches_oracle(gen, dist, dtype, shape):
     nrow, ncol, npad, G0, G1 = shape
     if dist == P.MRG_NORMAL and (ncol % 2 or G1 % 2):
         pytest.skip("normals need an even G1 and ncol")
-    if shape[3] * shape[4] > 4096 and dtype == P.MRG_F32:
-        pytest.skip("large lattice: f64 and raw cover it")
     seed = workloads.random_seed(nrow + 7 * ncol) % np.uint32(2147462579)
     rec = O.create_streams(OGEN[gen], seed, G0 * G1 + 5)
     run(gen, rec, nrow, ncol, npad, G0, G1, dist, dtype, 1.5)
