@@ -824,12 +824,10 @@ __global__ void __launch_bounds__(256) batch_finalize_kernel(BatchLaunch B) {
 
 // ------------------------------------------------------ stream creation
 // Stream i = J^i creator with J = A^Z (Z = 2^127, or 2^134 for MRG31k3p),
-// in two passes: create_starts_kernel computes stream 64w (the first stream
-// of each group of 64), and create_lanes_kernel takes stream 64w + l to J^l
-// times it.  J^i is the product of one table entry per nonzero base-64 digit
-// of i (StreamDigits: J^(v 64^d)), so a lane makes at most one matrix-vector
-// product per digit: one in create_lanes_kernel, at most five in
-// create_starts_kernel (i < 2^36).
+// in two steps: stream 64w (the first stream of each group of 64), then
+// stream 64w + l = J^l times it.  J^i is the product of one table entry per
+// nonzero base-64 digit of i (StreamDigits: J^(v 64^d)): at most five
+// matrix-vector products for a group's first stream (i < 2^36), one per lane.
 template <int G>
 __device__ __forceinline__ void write_record(uint32_t* rec, const uint32_t x[6]) {
 #pragma unroll
@@ -862,42 +860,45 @@ __device__ __forceinline__ void apply_f64(const double (&M)[2][9], double x[6]) 
     matvec_f64(M[1], x + 3, m2, 1.0 / m2);
 }
 
-// Stream 64 g for the group index g < 2^30: digit d of g is digit d + 1 of
-// the stream index.  ndig = base-64 digits of the largest group index.
+// Both passes in one launch: a block's 256 streams are four groups of 64,
+// whose first streams it makes itself (lanes 0-3, one product per nonzero
+// digit of the group index, the tables read from global memory), so no block
+// reads another's records.
 template <int G>
-__global__ void __launch_bounds__(256) create_starts_kernel(uint32_t* out, uint64_t n_groups, uint32_t c0,
-                                                            uint32_t c1, uint32_t c2, uint32_t c3, uint32_t c4,
-                                                            uint32_t c5, int ndig) {
-    __shared__ double tab[kStreamDigits - 1][64][2][9];  // J^(v 64^(d+1)), d < ndig <= 5
-    stage_digit_tables<G>(tab, 1, ndig);
-    const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= n_groups) return;
-    double x[6] = {static_cast<double>(c0), static_cast<double>(c1), static_cast<double>(c2),
-                   static_cast<double>(c3), static_cast<double>(c4), static_cast<double>(c5)};
-    for (int d = 0; d < ndig; ++d) {  // uniform loop; the digit is the lane's own
-        const uint32_t v = static_cast<uint32_t>(g >> (6 * d)) & 63u;
-        if (v) apply_f64<G>(tab[d][v], x);
-    }
-    uint32_t w[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) w[k] = static_cast<uint32_t>(x[k]);
-    write_record<G>(out + g * 64 * 18, w);
-}
-
-// The block's 256 records (18 KiB, contiguous in memory) are assembled in LDS
-// and written with coalesced dword stores.
-template <int G>
-__global__ void __launch_bounds__(256) create_lanes_kernel(uint32_t* out, uint64_t n) {
+__global__ void __launch_bounds__(256) create_kernel(uint32_t* out, uint64_t n, uint32_t c0, uint32_t c1,
+                                                     uint32_t c2, uint32_t c3, uint32_t c4, uint32_t c5,
+                                                     int ndig) {
     __shared__ double tab[1][64][2][9];  // J^v, v < 64
+    __shared__ double gstart[4][6];      // streams 64 g of the block's groups
     __shared__ uint32_t recs[256 * 18];
-    stage_digit_tables<G>(tab, 0, 1);
     const uint64_t first_i = static_cast<uint64_t>(blockIdx.x) * 256;
+    if (threadIdx.x < 4) {
+        const uint64_t g = first_i / 64 + threadIdx.x;
+        double x[6] = {static_cast<double>(c0), static_cast<double>(c1), static_cast<double>(c2),
+                       static_cast<double>(c3), static_cast<double>(c4), static_cast<double>(c5)};
+        if (g * 64 < n) {
+            for (int d = 0; d < ndig; ++d) {  // digit d of g is digit d + 1 of the stream index
+                const uint32_t v = static_cast<uint32_t>(g >> (6 * d)) & 63u;
+                if (v) {
+                    double M[2][9];
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) {
+                        M[0][e] = static_cast<double>(dev_dig<G>().digit[d + 1][0][v].a[e]);
+                        M[1][e] = static_cast<double>(dev_dig<G>().digit[d + 1][1][v].a[e]);
+                    }
+                    apply_f64<G>(M, x);
+                }
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < 6; ++w) gstart[threadIdx.x][w] = x[w];
+    }
+    stage_digit_tables<G>(tab, 0, 1);  // ends with a barrier every thread reaches: gstart is written
     const uint64_t i = first_i + threadIdx.x;
     if (i < n) {
-        const uint32_t* start = out + (i & ~static_cast<uint64_t>(63)) * 18;  // written by create_starts_kernel
         double x[6];
 #pragma unroll
-        for (int w = 0; w < 6; ++w) x[w] = static_cast<double>(start[w]);
+        for (int w = 0; w < 6; ++w) x[w] = gstart[threadIdx.x >> 6][w];
         const uint32_t v = static_cast<uint32_t>(i) & 63u;
         if (v) apply_f64<G>(tab[0][v], x);
         uint32_t w[6];
@@ -905,7 +906,7 @@ __global__ void __launch_bounds__(256) create_lanes_kernel(uint32_t* out, uint64
         for (int k = 0; k < 6; ++k) w[k] = static_cast<uint32_t>(x[k]);
         write_record<G>(recs + threadIdx.x * 18, w);
     }
-    __syncthreads();  // every group start of this block has been read
+    __syncthreads();
     const uint64_t n_here = n - first_i < 256 ? n - first_i : 256;
     const uint32_t words = static_cast<uint32_t>(n_here) * 18;
     uint32_t* dst = out + first_i * 18;
@@ -973,11 +974,8 @@ static hipError_t launch_create_t(uint32_t* out, uint64_t n, const uint32_t c[6]
     int ndig = 0;  // base-64 digits of the largest group index
     while (ndig < kStreamDigits && ((groups - 1) >> (6 * ndig))) ++ndig;
     if (ndig > kStreamDigits - 1) return hipErrorInvalidValue;  // more than 2^36 streams (refused by the API)
-    hipLaunchKernelGGL(create_starts_kernel<G>, dim3(grid1d(groups, 256)), dim3(256), 0, s, out, groups, c[0], c[1],
-                       c[2], c[3], c[4], c[5], ndig);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || n == 1) return e;
-    hipLaunchKernelGGL(create_lanes_kernel<G>, dim3(grid1d(n, 256)), dim3(256), 0, s, out, n);
+    hipLaunchKernelGGL(create_kernel<G>, dim3(grid1d(n, 256)), dim3(256), 0, s, out, n, c[0], c[1], c[2], c[3],
+                       c[4], c[5], ndig);
     return hipGetLastError();
 }
 
